@@ -1,0 +1,119 @@
+"""Benchmark of the hot path: one step = forward (energy, potential, field)
++ adjoint (dE/dx, dE/dq) of the equivalent-charge FMM on one GPU, inputs
+resident in HBM.  Prints one JSON line.
+
+Default workload: 262144 charges uniform in the unit cube, charges uniform
+in [-1, 1] minus their mean, 32^3 finest cells (l_f = 5), 4 points per axis,
+free boundary, FP32 arithmetic with FP64 energy reduction.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "hbm": 8000.0,            # GB/s
+    "fp32_mfma": 157.3,       # TFLOP/s
+    "fp64_mfma": 78.6,
+    "bf16_mfma": 2500.0,
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default=None, help="f64 | f32 | bf16far (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
+              "the multi-GPU spatial decomposition is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2212_13080_amd as eq
+    import workloads
+
+    w, pos, q = workloads.workload_inputs(args.config)
+    prec = {"f64": eq.FP64, "f32": eq.FP32, "bf16far": eq.FP32_BF16FAR, None: w.precision}[args.precision]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pt = torch.from_numpy(pos).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    plan = eq.Plan(w.levels, w.order, w.boundary, prec, device=dev)
+    ws = plan.workspace(w.n)
+    one = torch.ones((), dtype=torch.float64, device=dev)
+
+    def step():
+        E, phi, field = plan.forward(pt, qt, ws=ws)
+        dx, dq = plan.backward(qt, one, ws=ws)
+        return E, phi, field, dx, dq
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.profile(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = w.n / (ms * 1e-3)
+    print(f"[bench] {w.name}: {ms:.3f} ms/step, {value:.4g} particles/s", file=sys.stderr, flush=True)
+    for k, v in prof.items():
+        if v["launches"]:
+            print(f"[bench]   {k:8s} {v['ms'] / args.steps:8.4f} ms/step  launches/step "
+                  f"{v['launches'] / args.steps:.0f}", file=sys.stderr, flush=True)
+
+    m2l = prof["m2l"]
+    peak_key = {eq.FP64: "fp64_mfma", eq.FP32: "fp32_mfma", eq.FP32_BF16FAR: "bf16_mfma"}[prec]
+    achieved = m2l["flops"] / (m2l["ms"] * 1e-3) / 1e12 if m2l["ms"] > 0 else 0.0
+    roofline = {"kernel": "m2l", "bound": "mfma", "achieved": round(achieved, 3),
+                "peak": PEAKS[peak_key], "unit": "TFLOP/s", "frac": round(achieved / PEAKS[peak_key], 4),
+                "traffic": None,
+                "avg_launch_ms": round(m2l["ms"] / max(m2l["launches"], 1), 5),
+                "launches_per_step": m2l["launches"] / args.steps}
+
+    E, phi, field, dx, dq = out
+    result = {
+        "metric": "energy+force particles/s at 1e-5 rel. force error vs FP64 plain; % roofline",
+        "value": round(value, 1), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {eq.FP64: "f64", eq.FP32: "f32", eq.FP32_BF16FAR: "f32+bf16"}[prec],
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_charges": w.n, "levels": w.levels, "order": w.order,
+                   "boundary": workloads.BOUNDARY_NAMES[w.boundary]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        ref = oracle.fmm(pos, q, w.levels, w.order, w.boundary)
+        tc = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(w.n / tc, 1), "unit": "particles/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"one full evaluation of the same workload ({w.n} charges, "
+                                            f"potential+field+energy), {tc:.2f} s"}
+        F = (-dx.double().cpu().numpy())
+        Fr = q[:, None] * ref["field"]
+        result["rel_rms_force_err"] = float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr))
+        result["rel_energy_err"] = float(abs(E.item() - ref["energy"]) / abs(ref["energy"]))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
