@@ -35,6 +35,7 @@ struct DevOps {
     const void *K;          // Coulomb matrices [343][n3][n3] at unit cell side
     const void *T;          // periodic root operator [n3][n3] at unit box side
     const void *Kmx;        // matrix-core operand layout of K (precision specific)
+    const void *offs;       // interaction lists per parity: int8 [8][189][3]
 };
 
 // Host plan (the public opaque type).
@@ -80,7 +81,7 @@ struct eqfmm_plan {
     eqfmm::Geom g;
     eqfmm::HostOps h;
     std::vector<unsigned char> image;     // device image, built at create
-    size_t off_t, off_den, off_t64, off_seg, off_segden, off_G, off_K, off_T, off_Kmx;
+    size_t off_t, off_den, off_t64, off_seg, off_segden, off_G, off_K, off_T, off_Kmx, off_offs;
     void *dev = nullptr;
     eqfmm::DevOps ops{};
     // forward state consumed by backward

@@ -245,8 +245,8 @@ template <int N, typename R>
 __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const double *segden,
                                               int64_t n, const double *pos, const double *q,
                                               const int *fstart, const int *leafstart, int *cursor,
-                                              R *su, R *sv, R *sw, R *sq, int *spar, int *sleaf,
-                                              int *gslot, R *gw, R *gdw)
+                                              double *su, double *sv, double *sw, R *sq, int *spar,
+                                              int *sleaf, int *gslot, double *gw, double *gdw)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -265,17 +265,17 @@ __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const d
                 const int slot = leafstart[leaf] + atomicAdd(&cursor[leaf], 1);
                 const double ox = P[0].om[kx], oy = P[1].om[ky], oz = P[2].om[kz];
                 const double w = ox * oy * oz;
-                su[slot] = R(P[0].u[kx]);
-                sv[slot] = R(P[1].u[ky]);
-                sw[slot] = R(P[2].u[kz]);
+                su[slot] = P[0].u[kx];
+                sv[slot] = P[1].u[ky];
+                sw[slot] = P[2].u[kz];
                 sq[slot] = R(qi * w);
                 spar[slot] = int(i);
                 sleaf[slot] = leaf;
                 gslot[f] = slot;
-                gw[f] = R(w);
-                gdw[3 * int64_t(f) + 0] = R(P[0].dom[kx] * oy * oz);
-                gdw[3 * int64_t(f) + 1] = R(ox * P[1].dom[ky] * oz);
-                gdw[3 * int64_t(f) + 2] = R(ox * oy * P[2].dom[kz]);
+                gw[f] = w;
+                gdw[3 * int64_t(f) + 0] = P[0].dom[kx] * oy * oz;
+                gdw[3 * int64_t(f) + 1] = ox * P[1].dom[ky] * oz;
+                gdw[3 * int64_t(f) + 2] = ox * oy * P[2].dom[kz];
             }
 }
 
@@ -359,8 +359,8 @@ int scan(const int *in, int *out, int64_t len, int *blk, hipStream_t st)
 
 template <int N, typename R>
 __global__ void __launch_bounds__(512) k_p2m(const R *t_, const R *den_, int64_t nleaf,
-                                             const int *leafstart, const R *su, const R *sv,
-                                             const R *sw, const R *sq, R *phiL)
+                                             const int *leafstart, const double *su, const double *sv,
+                                             const double *sw, const R *sq, R *phiL)
 {
     using O = Ord<N>;
     constexpr int CPB = O::TPC >= 256 ? 1 : 256 / O::TPC;
@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(512) k_p2m(const R *t_, const R *den_, int64_t
         const int p0 = leafstart[c], p1 = leafstart[c + 1];
         for (int p = p0; p < p1; ++p) {
             R gx = den[i], gy = den[j], gz = den[k];
-            const R u = su[p], v = sv[p], w = sw[p];
+            const R u = R(su[p]), v = R(sv[p]), w = R(sw[p]);
 #pragma unroll
             for (int m = 0; m < N; ++m) {
                 if (m != i) gx *= u - t[m];
@@ -516,9 +516,9 @@ template <> __device__ __forceinline__ float rsq<float>(float x) { return rsqrtf
 // field over the same and 26 adjacent cells.  Storage type R, arithmetic C.
 template <int N, typename C, typename R>
 __device__ __forceinline__ void leaf_target(const Geom &g, const R *t_, const R *den_, int64_t p,
-                                            const int *leafstart, const R *su, const R *sv,
-                                            const R *sw, const R *sq, const int *spar,
-                                            const int *sleaf, const R *locL, R *sphi, R *sfld)
+                                            const int *leafstart, const double *su, const double *sv,
+                                            const double *sw, const R *sq, const int *spar,
+                                            const int *sleaf, const R *locL, double *sphi, R *sfld)
 {
     using O = Ord<N>;
     C t[N], den[N];
@@ -530,9 +530,11 @@ __device__ __forceinline__ void leaf_target(const Geom &g, const R *t_, const R 
     const int leaf = sleaf[p];
     const int D = g.D;
     const int cx = leaf % D, cy = (leaf / D) % D, cz = leaf / (D * D);
-    const C u = C(su[p]), v = C(sv[p]), w = C(sw[p]);
+    const double ud = su[p], vd = sv[p], wd = sw[p];
+    const C u = C(ud), v = C(vd), w = C(wd);
     const int par = spar[p];
     const C s = C(g.s_leaf), inv_s = C(1) / s;
+    const double sd = g.s_leaf;
     // far field: Psi_leaf evaluated on the replacement of a unit charge here
     C gx[N], gy[N], gz[N], dx[N], dy[N], dz[N];
     lag_vals_der<N>(t, den, u, gx, dx);
@@ -574,10 +576,13 @@ __device__ __forceinline__ void leaf_target(const Geom &g, const R *t_, const R 
                 }
                 const int nb = nx + D * (ny + D * nz);
                 const int j0 = leafstart[nb], j1 = leafstart[nb + 1];
-                const C ox = u - C(ddx), oy = v - C(ddy), oz = w - C(ddz);
+                // displacements are formed from the double cell-local
+                // coordinates: float coordinates would limit close pairs
+                // to ~1e-8 * side / r relative accuracy
+                const double ox = ud - ddx, oy = vd - ddy, oz = wd - ddz;
                 for (int j = j0; j < j1; ++j) {
                     if (spar[j] == par) continue;
-                    const C ex = (ox - C(su[j])) * s, ey = (oy - C(sv[j])) * s, ez = (oz - C(sw[j])) * s;
+                    const C ex = C((ox - su[j]) * sd), ey = C((oy - sv[j]) * sd), ez = C((oz - sw[j]) * sd);
                     const C r2 = ex * ex + ey * ey + ez * ez;
                     const C ri = rsq<C>(r2);
                     const C qr = C(sq[j]) * ri;
@@ -588,7 +593,7 @@ __device__ __forceinline__ void leaf_target(const Geom &g, const R *t_, const R 
                     f2 += qr3 * ez;
                 }
             }
-    sphi[p] = R(ph);
+    sphi[p] = double(ph);
     sfld[3 * p + 0] = R(f0);
     sfld[3 * p + 1] = R(f1);
     sfld[3 * p + 2] = R(f2);
@@ -599,10 +604,10 @@ __device__ __forceinline__ void leaf_target(const Geom &g, const R *t_, const R 
 // order 1/(2d), which amplifies float rounding in phi by about s/(2d).
 template <int N, typename R>
 __global__ void __launch_bounds__(256) k_leaf(Geom g, const R *t_, const R *den_, int64_t nfrag,
-                                              const int *leafstart, const R *su, const R *sv,
-                                              const R *sw, const R *sq, const int *spar,
+                                              const int *leafstart, const double *su, const double *sv,
+                                              const double *sw, const R *sq, const int *spar,
                                               const int *sleaf, const unsigned char *smask,
-                                              const R *locL, R *sphi, R *sfld)
+                                              const R *locL, double *sphi, R *sfld)
 {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= nfrag) return;
@@ -617,7 +622,7 @@ __global__ void __launch_bounds__(256) k_leaf(Geom g, const R *t_, const R *den_
 template <typename R>
 __global__ void __launch_bounds__(256) k_gather(int64_t n, const double *q, const int *fstart,
                                                 const unsigned char *smask, const int *gslot,
-                                                const R *gw, const R *gdw, const R *sphi,
+                                                const double *gw, const double *gdw, const double *sphi,
                                                 const R *sfld, R *phi_out, R *fld_out, double *epart)
 {
     __shared__ double red[256];
@@ -633,7 +638,7 @@ __global__ void __launch_bounds__(256) k_gather(int64_t n, const double *q, cons
             const double w = gw[f], pv = sphi[sl];
             ph += w * pv;
             for (int a = 0; a < 3; ++a) {
-                if (mask & (1 << a)) fe[a] -= double(gdw[3 * int64_t(f) + a]) * pv;
+                if (mask & (1 << a)) fe[a] -= gdw[3 * int64_t(f) + a] * pv;
                 else fe[a] += w * double(sfld[3 * int64_t(sl) + a]);
             }
         }
@@ -675,8 +680,8 @@ __global__ void __launch_bounds__(256) k_energy(const double *epart, int64_t nb,
 template <typename R>
 __global__ void __launch_bounds__(256) k_adjoint(int64_t n, const double *q, const double *gE,
                                                  const int *fstart, const unsigned char *smask,
-                                                 const int *gslot, const R *gw, const R *gdw,
-                                                 const R *sphi, const R *sfld, R *dEdx, R *dEdq)
+                                                 const int *gslot, const double *gw, const double *gdw,
+                                                 const double *sphi, const R *sfld, R *dEdx, R *dEdq)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -689,7 +694,7 @@ __global__ void __launch_bounds__(256) k_adjoint(int64_t n, const double *q, con
         const double w = gw[f], pv = sphi[sl];
         ph += w * pv;
         for (int a = 0; a < 3; ++a) {
-            if (mask & (1 << a)) gx[a] += double(gdw[3 * int64_t(f) + a]) * pv;
+            if (mask & (1 << a)) gx[a] += gdw[3 * int64_t(f) + a] * pv;
             else gx[a] -= w * double(sfld[3 * int64_t(sl) + a]);
         }
     }
@@ -706,8 +711,8 @@ template <typename R> struct Ws {
     WsHeader *hdr;
     int *cnt, *fstart, *leafcnt, *leafstart, *cursor, *scanblk, *spar, *sleaf, *gslot;
     unsigned char *smask;
-    R *su, *sv, *sw, *sq, *gw, *gdw, *phi, *loc, *sphi, *sfld;
-    double *epart;
+    R *sq, *phi, *loc, *sfld;
+    double *su, *sv, *sw, *gw, *gdw, *sphi, *epart;
 };
 
 template <typename R> Ws<R> views(unsigned char *b, const WsLayout &W)
@@ -721,18 +726,18 @@ template <typename R> Ws<R> views(unsigned char *b, const WsLayout &W)
     v.leafstart = reinterpret_cast<int *>(b + W.leafstart);
     v.cursor = reinterpret_cast<int *>(b + W.cursor);
     v.scanblk = reinterpret_cast<int *>(b + W.scanblk);
-    v.su = reinterpret_cast<R *>(b + W.su);
-    v.sv = reinterpret_cast<R *>(b + W.sv);
-    v.sw = reinterpret_cast<R *>(b + W.sw);
+    v.su = reinterpret_cast<double *>(b + W.su);
+    v.sv = reinterpret_cast<double *>(b + W.sv);
+    v.sw = reinterpret_cast<double *>(b + W.sw);
     v.sq = reinterpret_cast<R *>(b + W.sq);
     v.spar = reinterpret_cast<int *>(b + W.spar);
     v.sleaf = reinterpret_cast<int *>(b + W.sleaf);
     v.gslot = reinterpret_cast<int *>(b + W.gslot);
-    v.gw = reinterpret_cast<R *>(b + W.gw);
-    v.gdw = reinterpret_cast<R *>(b + W.gdw);
+    v.gw = reinterpret_cast<double *>(b + W.gw);
+    v.gdw = reinterpret_cast<double *>(b + W.gdw);
     v.phi = reinterpret_cast<R *>(b + W.phi);
     v.loc = reinterpret_cast<R *>(b + W.loc);
-    v.sphi = reinterpret_cast<R *>(b + W.sphi);
+    v.sphi = reinterpret_cast<double *>(b + W.sphi);
     v.sfld = reinterpret_cast<R *>(b + W.sfld);
     v.epart = reinterpret_cast<double *>(b + W.epart);
     return v;
@@ -744,7 +749,7 @@ unsigned blocks(int64_t work, int per) { return unsigned((work + per - 1) / per)
 
 // far field at one level (declared here, defined with the matrix-core kernels)
 template <typename R>
-int launch_m2l(eqfmm_plan *plan, int level, const R *phi_l, R *loc_l, hipStream_t st);
+int launch_m2l(eqfmm_plan *plan, int level, const R *phi_l, const R *zrow, R *loc_l, hipStream_t st);
 
 template <int N, typename R>
 int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi_out,
@@ -764,6 +769,9 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     EQ_CHECK(hipMemsetAsync(v.hdr, 0, sizeof(WsHeader), st));
     EQ_CHECK(hipMemsetAsync(v.leafcnt, 0, 4 * (nleaf + 1), st));
     EQ_CHECK(hipMemsetAsync(v.cursor, 0, 4 * nleaf, st));
+    // a row of zeros after the last level: the far-field kernels read it for
+    // sources outside the box
+    EQ_CHECK(hipMemsetAsync(v.phi + W.lvl[g.L + 1] * O::NS, 0, O::NS * rs, st));
     k_count<N><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, n, pos, q, v.cnt, v.smask, v.leafcnt, v.hdr);
     EQ_CHECK(hipGetLastError());
     int rc = scan(v.cnt, v.fstart, n, v.scanblk, st);
@@ -832,7 +840,8 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
             EQ_CHECK(hipGetLastError());
             prof_end(plan, st, pk, EQFMM_STAGE_L2L, 0.0, 0.0);
         }
-        rc = launch_m2l<R>(plan, l, v.phi + W.lvl[l] * O::NS, v.loc + W.lvl[l] * O::NS, st);
+        rc = launch_m2l<R>(plan, l, v.phi + W.lvl[l] * O::NS, v.phi + W.lvl[L + 1] * O::NS,
+                           v.loc + W.lvl[l] * O::NS, st);
         if (rc) return rc;
     }
 

@@ -12,15 +12,16 @@
 //   C[cell][node] += sum_k Phi_src(cell)[k] K_o[node][k]
 // product.  The source-node axis k is split in two halves, one per half
 // wave, so that each lane streams one contiguous half row of Phi and of K_o.
-// Each displacement's product is summed in a fresh float accumulator and
-// folded into double sums: the far-field terms cancel heavily (charges of
-// both signs), and plain float accumulation over the whole list would lose
-// about an order of magnitude of accuracy.
+// Each displacement's product is summed in a fresh float accumulator pair
+// and only then added to the running sums: the far-field terms cancel
+// heavily (charges of both signs), and one float accumulation chain over
+// the whole list loses about an order of magnitude of accuracy.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -47,6 +48,16 @@ __device__ __forceinline__ int compact3(int64_t m)
 
 int nb_of(int n3) { return (n3 + 31) / 32; }
 
+// compile-time loop: f(integral_constant<int, I>) for I in [B, E)
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ operand layout
@@ -55,33 +66,57 @@ int nb_of(int n3) { return (n3 + 31) / 32; }
 // K_o[nb*32 + j][g*KH + s]; stored [oi][nb][s/4][lane][s%4] (one 16-byte
 // load per lane per four steps).  BF16: eight consecutive steps per lane,
 // [oi][nb][s/8][lane][s%8].
+// bytes of the float layout; the bf16 mode stores the float layout (coarse
+// levels) followed by the bf16 one (the two finest levels)
+size_t mx_f32_bytes(const Geom &g) { return size_t(kNumOffsets) * nb_of(g.n3) * (g.ns / 2) * 64 * sizeof(float); }
+
 size_t mx_layout_bytes(const Geom &g, int precision)
 {
-    if (precision == EQFMM_FP64) return 0;
-    const size_t elem = precision == EQFMM_FP32 ? sizeof(float) : sizeof(__hip_bfloat16);
-    return size_t(kNumOffsets) * nb_of(g.n3) * (g.ns / 2) * 64 * elem;
+    if (precision == EQFMM_FP64)   // [oi][nb16][s/2][lane][s%2], KQ = ns/4 steps
+        return size_t(kNumOffsets) * ((g.n3 + 15) / 16) * (g.ns / 4) * 64 * sizeof(double);
+    if (precision == EQFMM_FP32) return mx_f32_bytes(g);
+    return mx_f32_bytes(g) + mx_f32_bytes(g) / 2;
 }
 
 void mx_layout_fill(const Geom &g, int precision, const std::vector<double> &K, unsigned char *dst)
 {
-    if (precision == EQFMM_FP64) return;
-    const int n3 = g.n3, KH = g.ns / 2, NB = nb_of(n3);
-    const int V = precision == EQFMM_FP32 ? 4 : 8;
-    for (int oi = 0; oi < kNumOffsets; ++oi)
-        for (int nb = 0; nb < NB; ++nb)
-            for (int s = 0; s < KH; ++s)
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int j = nb * 32 + (lane & 31);
-                    const int k = (lane >> 5) * KH + s;
-                    const double v = (j < n3 && k < n3) ? K[(size_t(oi) * n3 + j) * n3 + k] : 0.0;
-                    const size_t idx = ((((size_t(oi) * NB + nb) * (KH / V) + s / V) * 64 + lane) * V) + s % V;
-                    if (precision == EQFMM_FP32) {
-                        reinterpret_cast<float *>(dst)[idx] = float(v);
-                    } else {
-                        __hip_bfloat16 b = __float2bfloat16(float(v));
-                        std::memcpy(dst + idx * 2, &b, 2);
+    if (precision == EQFMM_FP64) {
+        // v_mfma_f64_16x16x4f64: lane l (node j = l % 16, quarter g = l / 16)
+        // at step s supplies K_o[nb*16 + j][g*KQ + s]
+        const int n3 = g.n3, KQ = g.ns / 4, NB = (n3 + 15) / 16;
+        double *d = reinterpret_cast<double *>(dst);
+        for (int oi = 0; oi < kNumOffsets; ++oi)
+            for (int nb = 0; nb < NB; ++nb)
+                for (int s = 0; s < KQ; ++s)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int j = nb * 16 + (lane & 15);
+                        const int k = (lane >> 4) * KQ + s;
+                        const double v = (j < n3 && k < n3) ? K[(size_t(oi) * n3 + j) * n3 + k] : 0.0;
+                        d[((((size_t(oi) * NB + nb) * (KQ / 2) + s / 2) * 64 + lane) * 2) + s % 2] = v;
                     }
-                }
+        return;
+    }
+    const int n3 = g.n3, KH = g.ns / 2, NB = nb_of(n3);
+    for (int pass = 0; pass < (precision == EQFMM_FP32 ? 1 : 2); ++pass) {
+        const int V = pass == 0 ? 4 : 8;
+        unsigned char *base = pass == 0 ? dst : dst + mx_f32_bytes(g);
+        for (int oi = 0; oi < kNumOffsets; ++oi)
+            for (int nb = 0; nb < NB; ++nb)
+                for (int s = 0; s < KH; ++s)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int j = nb * 32 + (lane & 31);
+                        const int k = (lane >> 5) * KH + s;
+                        const double v = (j < n3 && k < n3) ? K[(size_t(oi) * n3 + j) * n3 + k] : 0.0;
+                        const size_t idx =
+                            ((((size_t(oi) * NB + nb) * (KH / V) + s / V) * 64 + lane) * V) + s % V;
+                        if (pass == 0) {
+                            reinterpret_cast<float *>(base)[idx] = float(v);
+                        } else {
+                            __hip_bfloat16 b = __float2bfloat16(float(v));
+                            std::memcpy(base + idx * 2, &b, 2);
+                        }
+                    }
+    }
 }
 
 // --------------------------------------------------------------- kernels
@@ -90,13 +125,25 @@ void mx_layout_fill(const Geom &g, int precision, const std::vector<double> &K, 
 // workgroup id is remapped so that each of the 8 XCDs gets a contiguous
 // range of (parity, node block, tile) work, i.e. mostly one parity and
 // hence one set of 189 matrices in its L2.
-template <int N, bool BF16>
-__global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__ Kmx, int level,
+//
+// The walk over (displacement, k-chunk) steps is software pipelined: the
+// operands of step s+1 are loaded into the second register stage while the
+// matrix cores work on step s.  Each displacement's product goes to a fresh
+// accumulator pair that is added to float running sums when the
+// displacement is complete.
+template <int N, bool BF16, int CH, bool PERIODIC>
+__global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__ Kmx,
+                                                const signed char *__restrict__ offs, int level,
                                                 float inv_side, const float *__restrict__ phi,
+                                                const float *__restrict__ zrow,
                                                 float *__restrict__ loc, int ntile, int nwg)
 {
     using S = MxShape<N>;
     constexpr int NS = S::NS, KH = S::KH, NB = S::NB;
+    constexpr int NA = KH / 4;            // float4 loads of one half row
+    constexpr int NCH = NA / CH;          // pipeline steps per displacement
+    static_assert(NA % CH == 0, "chunking");
+    static_assert(!BF16 || CH % 2 == 0, "bf16 steps take 8 sources per lane");
     const int per = gridDim.x >> 3;
     const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (wg >= nwg) return;
@@ -105,76 +152,114 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     const int nb = pn % NB, p = pn / NB;
     const int lane = threadIdx.x & 63;
     const int t = tg * 4 + (threadIdx.x >> 6);
+    // the interaction list of this parity, packed (ox+3) | (oy+3) << 4 | (oz+3) << 8
+    __shared__ int soff[189];
+    if (threadIdx.x < 189) {
+        const signed char *q = offs + (p * 189 + threadIdx.x) * 3;
+        soff[threadIdx.x] = (q[0] + 3) | ((q[1] + 3) << 4) | ((q[2] + 3) << 8);
+    }
+    __syncthreads();
     if (t >= ntile) return;
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
     const int D = 1 << level, Dp = D >> 1;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
-    // A-operand row: cell i = lane % 32 of this tile, source half gh
     const int i = lane & 31, gh = lane >> 5;
     const int64_t Pm = int64_t(t) * 32 + i;
     const bool cvalid = Pm < nparent;
     const int cx = 2 * compact3(Pm) + px, cy = 2 * compact3(Pm >> 1) + py, cz = 2 * compact3(Pm >> 2) + pz;
 
-    double sum[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) sum[r] = 0.0;
+    const int nsteps = 189 * NCH;
+    float4 abuf[2][CH];
+    using BT = typename std::conditional<BF16, bf16x8, float4>::type;
+    constexpr int NBL = BF16 ? CH / 2 : CH;   // B loads per step
+    BT bbuf[2][NBL];
 
-    for (int oz = -2 - pz; oz <= 3 - pz; ++oz)
-        for (int oy = -2 - py; oy <= 3 - py; ++oy)
-            for (int ox = -2 - px; ox <= 3 - px; ++ox) {
-                if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1 && oz >= -1 && oz <= 1) continue;
-                int sx = cx + ox, sy = cy + oy, sz = cz + oz;
-                bool valid = cvalid;
-                if (g.periodic) {
-                    sx &= D - 1;
-                    sy &= D - 1;
-                    sz &= D - 1;
-                } else {
-                    valid = valid && sx >= 0 && sy >= 0 && sz >= 0 && sx < D && sy < D && sz < D;
-                }
-                if (__ballot(valid) == 0) continue;
-                const int64_t src = valid ? sx + int64_t(D) * (sy + int64_t(D) * sz) : 0;
-                const float *ap = phi + src * NS + gh * KH;
-                const int oi = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
-                floatx16 c0 = {}, c1 = {};
-                if constexpr (!BF16) {
-                    const float4 *bp = reinterpret_cast<const float4 *>(Kmx) +
-                                       (size_t(oi) * NB + nb) * (KH / 4) * 64 + lane;
+    // Loads of step `step` (clamped, so that the loop body is branch free and
+    // the wait counts stay exact); a source outside the box (free space)
+    // reads a row of zeros.
+    auto issue = [&](int step, auto bc) {
+        constexpr int b = decltype(bc)::value;
+        step = step < nsteps ? step : nsteps - 1;
+        const int oidx = step / NCH, ch = step - oidx * NCH;
+        const int pk = soff[oidx];
+        const int ox = (pk & 15) - 3, oy = ((pk >> 4) & 15) - 3, oz = (pk >> 8) - 3;
+        int sx = cx + ox, sy = cy + oy, sz = cz + oz;
+        bool valid = cvalid;
+        if constexpr (PERIODIC) {
+            sx &= D - 1;
+            sy &= D - 1;
+            sz &= D - 1;
+        } else {
+            valid = valid && sx >= 0 && sy >= 0 && sz >= 0 && sx < D && sy < D && sz < D;
+        }
+        const float *row = valid ? phi + (sx + int64_t(D) * (sy + int64_t(D) * sz)) * NS : zrow;
+        const float4 *ap = reinterpret_cast<const float4 *>(row + gh * KH) + ch * CH;
 #pragma unroll
-                    for (int s4 = 0; s4 < KH / 4; ++s4) {
-                        float4 a = *reinterpret_cast<const float4 *>(ap + 4 * s4);
-                        const float4 b = bp[s4 * 64];
-                        if (!valid) a = make_float4(0.f, 0.f, 0.f, 0.f);
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, c0, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, c1, 0, 0, 0);
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, c0, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, c1, 0, 0, 0);
-                    }
-                } else {
-                    const bf16x8 *bp = reinterpret_cast<const bf16x8 *>(Kmx) +
-                                       (size_t(oi) * NB + nb) * (KH / 8) * 64 + lane;
+        for (int c = 0; c < CH; ++c) abuf[b][c] = ap[c];
+        const int oi = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
+        const BT *bp = reinterpret_cast<const BT *>(Kmx) + ((size_t(oi) * NB + nb) * (NA * 4 / (BF16 ? 8 : 4)) +
+                                                            ch * NBL) * 64 + lane;
 #pragma unroll
-                    for (int s8 = 0; s8 < KH / 8; ++s8) {
-                        const float4 a0 = *reinterpret_cast<const float4 *>(ap + 8 * s8);
-                        const float4 a1 = *reinterpret_cast<const float4 *>(ap + 8 * s8 + 4);
-                        const bf16x8 b = bp[s8 * 64];
-                        const float m = valid ? 1.f : 0.f;
-                        bf16x8 a;
-                        a[0] = __bf16(a0.x * m);
-                        a[1] = __bf16(a0.y * m);
-                        a[2] = __bf16(a0.z * m);
-                        a[3] = __bf16(a0.w * m);
-                        a[4] = __bf16(a1.x * m);
-                        a[5] = __bf16(a1.y * m);
-                        a[6] = __bf16(a1.z * m);
-                        a[7] = __bf16(a1.w * m);
-                        if (s8 & 1) c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
-                        else c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c0, 0, 0, 0);
-                    }
-                }
+        for (int c = 0; c < NBL; ++c) bbuf[b][c] = bp[c * 64];
+    };
+
+    floatx16 c0 = {}, c1 = {}, run = {};
+    // one k-chunk of one displacement from register stage b
+    auto compute = [&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        if constexpr (!BF16) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) sum[r] += double(c0[r]) + double(c1[r]);
+            for (int c = 0; c < CH; ++c) {
+                const float4 a = abuf[b][c];
+                const float4 bb = bbuf[b][c];
+                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bb.x, c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bb.y, c1, 0, 0, 0);
+                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bb.z, c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bb.w, c1, 0, 0, 0);
             }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NBL; ++c) {
+                const float4 a0 = abuf[b][2 * c], a1 = abuf[b][2 * c + 1];
+                bf16x8 a;
+                a[0] = __bf16(a0.x);
+                a[1] = __bf16(a0.y);
+                a[2] = __bf16(a0.z);
+                a[3] = __bf16(a0.w);
+                a[4] = __bf16(a1.x);
+                a[5] = __bf16(a1.y);
+                a[6] = __bf16(a1.z);
+                a[7] = __bf16(a1.w);
+                if (c & 1) c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], c1, 0, 0, 0);
+                else c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], c0, 0, 0, 0);
+            }
+        }
+    };
+
+    // Two displacements (2 * NCH steps) per trip, unrolled at compile time so
+    // that the register stage of every step is a constant and the body has
+    // no branches; the second displacement of the last trip is a clamped
+    // repeat whose sum is discarded.
+    issue(0, std::integral_constant<int, 0>{});
+    for (int op = 0; op < 189; op += 2) {
+        static_for<0, 2 * NCH>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr int b = j & 1;
+            constexpr int ch = j % NCH;
+            issue(op * NCH + j + 1, std::integral_constant<int, 1 - b>{});
+            // keep the loads of the next step ahead of this step's products
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (ch == 0) {
+                c0 = floatx16{};
+                c1 = floatx16{};
+            }
+            compute(std::integral_constant<int, b>{});
+            if constexpr (ch == NCH - 1) {
+                const float keep = op + j / NCH < 189 ? 1.f : 0.f;
+                run += (c0 + c1) * keep;
+            }
+        });
+    }
 
     // C[cell][node]: lane l, register r -> node j = l % 32, cell
     // ii = 4 (l / 32) + (r % 4) + 8 (r / 4)
@@ -187,43 +272,113 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
         if (P2 >= nparent) continue;
         const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
         const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
-        loc[c * NS + j] += inv_side * float(sum[r]);
+        loc[c * NS + j] += inv_side * run[r];
     }
 }
 
-// Plain double-precision kernel: one thread per (cell, node).
-template <typename R>
-__global__ void __launch_bounds__(256) k_m2l_valu(Geom g, const R *K, int Dl, R inv_side,
-                                                  const R *phi, R *loc)
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// Double precision on the matrix cores (v_mfma_f64_16x16x4f64): a wave owns
+// 16 target cells of one parity (16 parents consecutive in Morton order) and
+// 16 target nodes; the source axis is split in four quarters, one per
+// quarter wave.  Same pipelining as the float kernel.
+template <int N, int CH, bool PERIODIC>
+__global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restrict__ Kmx,
+                                                 const signed char *__restrict__ offs, int level,
+                                                 double inv_side, const double *__restrict__ phi,
+                                                 const double *__restrict__ zrow,
+                                                 double *__restrict__ loc, int ntile, int nwg)
 {
-    const int n3 = g.n3, ns = g.ns;
-    const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t c = gid / ns;
-    const int a = int(gid % ns);
-    const int64_t ncell = int64_t(Dl) * Dl * Dl;
-    if (c >= ncell || a >= n3) return;
-    const int x = int(c % Dl), y = int((c / Dl) % Dl), z = int(c / (int64_t(Dl) * Dl));
-    const int px = x & 1, py = y & 1, pz = z & 1;
-    R acc = R(0);
-    for (int oz = -2 - pz; oz <= 3 - pz; ++oz)
-        for (int oy = -2 - py; oy <= 3 - py; ++oy)
-            for (int ox = -2 - px; ox <= 3 - px; ++ox) {
-                if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1 && oz >= -1 && oz <= 1) continue;
-                int sx = x + ox, sy = y + oy, sz = z + oz;
-                if (g.periodic) {
-                    sx = (sx + 4 * Dl) % Dl;
-                    sy = (sy + 4 * Dl) % Dl;
-                    sz = (sz + 4 * Dl) % Dl;
-                } else if (sx < 0 || sy < 0 || sz < 0 || sx >= Dl || sy >= Dl || sz >= Dl) {
-                    continue;
-                }
-                const int64_t src = sx + int64_t(Dl) * (sy + int64_t(Dl) * sz);
-                const int oi = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
-                const R *Kr = K + (int64_t(oi) * n3 + a) * n3;
-                const R *ps = phi + src * ns;
-                for (int b = 0; b < n3; ++b) acc += Kr[b] * ps[b];
+    constexpr int N3 = N * N * N, NS = (N3 + 15) & ~15, KQ = NS / 4, NB = (N3 + 15) / 16;
+    constexpr int NA = KQ / 2;            // double2 loads of one quarter row
+    constexpr int NCH = NA / CH;
+    static_assert(NA % CH == 0, "chunking");
+    const int per = gridDim.x >> 3;
+    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (wg >= nwg) return;
+    const int ntg = (ntile + 3) >> 2;
+    const int tg = wg % ntg, pn = wg / ntg;
+    const int nb = pn % NB, p = pn / NB;
+    const int lane = threadIdx.x & 63;
+    const int t = tg * 4 + (threadIdx.x >> 6);
+    __shared__ int soff[189];
+    if (threadIdx.x < 189) {
+        const signed char *q = offs + (p * 189 + threadIdx.x) * 3;
+        soff[threadIdx.x] = (q[0] + 3) | ((q[1] + 3) << 4) | ((q[2] + 3) << 8);
+    }
+    __syncthreads();
+    if (t >= ntile) return;
+    const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+    const int D = 1 << level, Dp = D >> 1;
+    const int64_t nparent = int64_t(Dp) * Dp * Dp;
+    const int i = lane & 15, gq = lane >> 4;
+    const int64_t Pm = int64_t(t) * 16 + i;
+    const bool cvalid = Pm < nparent;
+    const int cx = 2 * compact3(Pm) + px, cy = 2 * compact3(Pm >> 1) + py, cz = 2 * compact3(Pm >> 2) + pz;
+    double2 abuf[2][CH], bbuf[2][CH];
+
+    auto issue = [&](int step, auto bc) {
+        constexpr int b = decltype(bc)::value;
+        constexpr int nsteps = 189 * NCH;
+        step = step < nsteps ? step : nsteps - 1;
+        const int oidx = step / NCH, ch = step - oidx * NCH;
+        const int pk = soff[oidx];
+        const int ox = (pk & 15) - 3, oy = ((pk >> 4) & 15) - 3, oz = (pk >> 8) - 3;
+        int sx = cx + ox, sy = cy + oy, sz = cz + oz;
+        bool valid = cvalid;
+        if constexpr (PERIODIC) {
+            sx &= D - 1;
+            sy &= D - 1;
+            sz &= D - 1;
+        } else {
+            valid = valid && sx >= 0 && sy >= 0 && sz >= 0 && sx < D && sy < D && sz < D;
+        }
+        const double *row = valid ? phi + (sx + int64_t(D) * (sy + int64_t(D) * sz)) * NS : zrow;
+        const double2 *ap = reinterpret_cast<const double2 *>(row + gq * KQ) + ch * CH;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) abuf[b][c] = ap[c];
+        const int oi = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
+        const double2 *bp = Kmx + ((size_t(oi) * NB + nb) * NA + ch * CH) * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) bbuf[b][c] = bp[c * 64];
+    };
+
+    doublex4 c0 = {}, c1 = {}, run = {};
+    issue(0, std::integral_constant<int, 0>{});
+    for (int op = 0; op < 189; op += 2) {
+        static_for<0, 2 * NCH>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr int b = j & 1;
+            constexpr int ch = j % NCH;
+            issue(op * NCH + j + 1, std::integral_constant<int, 1 - b>{});
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (ch == 0) {
+                c0 = doublex4{};
+                c1 = doublex4{};
             }
-    loc[c * ns + a] += inv_side * acc;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[b][c].x, bbuf[b][c].x, c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[b][c].y, bbuf[b][c].y, c1, 0, 0, 0);
+            }
+            if constexpr (ch == NCH - 1) {
+                const double keep = op + j / NCH < 189 ? 1.0 : 0.0;
+                run += (c0 + c1) * keep;
+            }
+        });
+    }
+    // lane l, register r -> node j = l % 16, cell ii = l / 16 + 4 r
+    const int j = nb * 16 + (lane & 15);
+    if (j >= N3) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ii = (lane >> 4) + 4 * r;
+        const int64_t P2 = int64_t(t) * 16 + ii;
+        if (P2 >= nparent) continue;
+        const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
+        const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
+        loc[c * NS + j] += inv_side * run[r];
+    }
 }
 
 // --------------------------------------------------------------- launcher
@@ -249,10 +404,17 @@ double il_pairs(const Geom &g, int level)
     return double(A) * A * A - double(B) * B * B;
 }
 
+template <int N> struct MxChunk {
+    static constexpr int NA = MxShape<N>::KH / 4;
+    static constexpr int CH = NA % 8 == 0 ? 8 : (NA % 4 == 0 ? 4 : NA);
+};
+
 template <int N>
-int launch_mx(eqfmm_plan *plan, int level, const float *phi_l, float *loc_l, hipStream_t st)
+int launch_mx(eqfmm_plan *plan, int level, const float *phi_l, const float *zrow, float *loc_l,
+              hipStream_t st)
 {
     using S = MxShape<N>;
+    constexpr int CH = MxChunk<N>::CH;
     const Geom &g = plan->g;
     const int Dp = (1 << level) >> 1;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
@@ -260,31 +422,42 @@ int launch_mx(eqfmm_plan *plan, int level, const float *phi_l, float *loc_l, hip
     const int nwg = 8 * S::NB * ((ntile + 3) / 4);
     const int grid = (nwg + 7) & ~7;
     const float inv_side = float(double(1 << level) / g.box);
-    if (plan->p.precision == EQFMM_FP32_BF16FAR)
-        k_m2l_mx<N, true><<<grid, 256, 0, st>>>(g, plan->ops.Kmx, level, inv_side, phi_l, loc_l, ntile, nwg);
-    else
-        k_m2l_mx<N, false><<<grid, 256, 0, st>>>(g, plan->ops.Kmx, level, inv_side, phi_l, loc_l, ntile, nwg);
+    const signed char *offs = static_cast<const signed char *>(plan->ops.offs);
+    // bf16 inputs only on the two finest levels, which carry nearly all the
+    // work; on coarse levels the cells hold many charges and bf16 rounding of
+    // their large, sign-cancelling vectors leaves a spurious net charge
+    const bool bf = plan->p.precision == EQFMM_FP32_BF16FAR && level >= g.L - 1;
+    const void *Kl = bf ? static_cast<const unsigned char *>(plan->ops.Kmx) + mx_f32_bytes(g) : plan->ops.Kmx;
+#define EQ_M2L_LAUNCH(B, P)                                                                      \
+    k_m2l_mx<N, B, CH, P><<<grid, 256, 0, st>>>(g, Kl, offs, level, inv_side, phi_l, zrow,        \
+                                                loc_l, ntile, nwg)
+    if (bf && g.periodic) EQ_M2L_LAUNCH(true, true);
+    else if (bf) EQ_M2L_LAUNCH(true, false);
+    else if (g.periodic) EQ_M2L_LAUNCH(false, true);
+    else EQ_M2L_LAUNCH(false, false);
+#undef EQ_M2L_LAUNCH
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
 
 }  // namespace
 
 template <typename R>
-int launch_m2l(eqfmm_plan *plan, int level, const R *phi_l, R *loc_l, hipStream_t st);
+int launch_m2l(eqfmm_plan *plan, int level, const R *phi_l, const R *zrow, R *loc_l, hipStream_t st);
 
 template <>
-int launch_m2l<float>(eqfmm_plan *plan, int level, const float *phi_l, float *loc_l, hipStream_t st)
+int launch_m2l<float>(eqfmm_plan *plan, int level, const float *phi_l, const float *zrow, float *loc_l,
+                      hipStream_t st)
 {
     const Geom &g = plan->g;
     const int pk = prof_begin_m2l(plan, st);
     int rc;
     switch (g.n) {
-        case 2: rc = launch_mx<2>(plan, level, phi_l, loc_l, st); break;
-        case 3: rc = launch_mx<3>(plan, level, phi_l, loc_l, st); break;
-        case 4: rc = launch_mx<4>(plan, level, phi_l, loc_l, st); break;
-        case 5: rc = launch_mx<5>(plan, level, phi_l, loc_l, st); break;
-        case 6: rc = launch_mx<6>(plan, level, phi_l, loc_l, st); break;
-        case 7: rc = launch_mx<7>(plan, level, phi_l, loc_l, st); break;
+        case 2: rc = launch_mx<2>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 3: rc = launch_mx<3>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 4: rc = launch_mx<4>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 5: rc = launch_mx<5>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 6: rc = launch_mx<6>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 7: rc = launch_mx<7>(plan, level, phi_l, zrow, loc_l, st); break;
         default: rc = EQFMM_EINVAL;
     }
     const int64_t ncell = int64_t(1) << (3 * level);
@@ -293,17 +466,50 @@ int launch_m2l<float>(eqfmm_plan *plan, int level, const float *phi_l, float *lo
     return rc;
 }
 
+namespace {
+
+template <int N>
+int launch_f64(eqfmm_plan *plan, int level, const double *phi_l, const double *zrow, double *loc_l,
+               hipStream_t st)
+{
+    constexpr int NA = ((N * N * N + 15) & ~15) / 8;
+    constexpr int CH = NA % 4 == 0 ? 4 : (NA % 2 == 0 ? 2 : 1);
+    constexpr int NB = (N * N * N + 15) / 16;
+    const Geom &g = plan->g;
+    const int Dp = (1 << level) >> 1;
+    const int64_t nparent = int64_t(Dp) * Dp * Dp;
+    const int ntile = int((nparent + 15) / 16);
+    const int nwg = 8 * NB * ((ntile + 3) / 4);
+    const int grid = (nwg + 7) & ~7;
+    const double inv_side = double(1 << level) / g.box;
+    const double2 *K = static_cast<const double2 *>(plan->ops.Kmx);
+    const signed char *offs = static_cast<const signed char *>(plan->ops.offs);
+    if (g.periodic)
+        k_m2l_f64<N, CH, true><<<grid, 256, 0, st>>>(g, K, offs, level, inv_side, phi_l, zrow, loc_l, ntile, nwg);
+    else
+        k_m2l_f64<N, CH, false><<<grid, 256, 0, st>>>(g, K, offs, level, inv_side, phi_l, zrow, loc_l, ntile, nwg);
+    return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+}
+
+}  // namespace
+
 template <>
-int launch_m2l<double>(eqfmm_plan *plan, int level, const double *phi_l, double *loc_l, hipStream_t st)
+int launch_m2l<double>(eqfmm_plan *plan, int level, const double *phi_l, const double *zrow,
+                       double *loc_l, hipStream_t st)
 {
     const Geom &g = plan->g;
-    const int Dl = 1 << level;
-    const int64_t ncell = int64_t(Dl) * Dl * Dl;
     const int pk = prof_begin_m2l(plan, st);
-    const int64_t work = ncell * g.ns;
-    k_m2l_valu<double><<<unsigned((work + 255) / 256), 256, 0, st>>>(
-        g, static_cast<const double *>(plan->ops.K), Dl, double(Dl) / g.box, phi_l, loc_l);
-    const int rc = hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+    int rc;
+    switch (g.n) {
+        case 2: rc = launch_f64<2>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 3: rc = launch_f64<3>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 4: rc = launch_f64<4>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 5: rc = launch_f64<5>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 6: rc = launch_f64<6>(plan, level, phi_l, zrow, loc_l, st); break;
+        case 7: rc = launch_f64<7>(plan, level, phi_l, zrow, loc_l, st); break;
+        default: rc = EQFMM_EINVAL;
+    }
+    const int64_t ncell = int64_t(1) << (3 * level);
     prof_end_m2l(plan, st, pk, 2.0 * double(g.n3) * g.n3 * il_pairs(g, level),
                  double(ncell) * g.ns * sizeof(double) * 3.0);
     return rc;

@@ -165,7 +165,26 @@ int build_image(eqfmm_plan *plan)
     plan->off_K = take(rs * h.K.size());
     plan->off_T = take(rs * std::max<size_t>(h.T.size(), 1));
     plan->off_Kmx = take(std::max<size_t>(mx_layout_bytes(g, prec), 1));
+    plan->off_offs = take(8 * 189 * 3);
     plan->image.assign(off, 0);
+    // interaction list of a cell with parity p (cell index mod 2 per axis):
+    // displacements in [-2-p, 3-p]^3 that are not adjacent
+    {
+        signed char *o = reinterpret_cast<signed char *>(plan->image.data() + plan->off_offs);
+        for (int p = 0; p < 8; ++p) {
+            const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+            int m = 0;
+            for (int oz = -2 - pz; oz <= 3 - pz; ++oz)
+                for (int oy = -2 - py; oy <= 3 - py; ++oy)
+                    for (int ox = -2 - px; ox <= 3 - px; ++ox) {
+                        if (std::abs(ox) <= 1 && std::abs(oy) <= 1 && std::abs(oz) <= 1) continue;
+                        o[(p * 189 + m) * 3 + 0] = static_cast<signed char>(ox);
+                        o[(p * 189 + m) * 3 + 1] = static_cast<signed char>(oy);
+                        o[(p * 189 + m) * 3 + 2] = static_cast<signed char>(oz);
+                        ++m;
+                    }
+        }
+    }
     auto &img = plan->image;
     if (prec == EQFMM_FP64) {
         put<double>(img, plan->off_t, h.t);
@@ -215,18 +234,21 @@ WsLayout ws_layout(const eqfmm_plan *plan, int64_t n)
     W.leafstart = take(4 * (W.nleaf + 1));
     W.cursor = take(4 * W.nleaf);
     W.scanblk = take(4 * (W.scan_blocks + 1));
-    W.su = take(rs * W.fcap);
-    W.sv = take(rs * W.fcap);
-    W.sw = take(rs * W.fcap);
+    // cell-local coordinates in double in every mode (close pairs)
+    W.su = take(sizeof(double) * W.fcap);
+    W.sv = take(sizeof(double) * W.fcap);
+    W.sw = take(sizeof(double) * W.fcap);
     W.sq = take(rs * W.fcap);
     W.spar = take(4 * W.fcap);
     W.sleaf = take(4 * W.fcap);
     W.gslot = take(4 * W.fcap);
-    W.gw = take(rs * W.fcap);
-    W.gdw = take(rs * 3 * W.fcap);
-    W.phi = take(rs * ncells * g.ns);
+    // split weights and fragment potentials in double in every mode: along a
+    // split axis the force is a short sum of large cancelling terms
+    W.gw = take(sizeof(double) * W.fcap);
+    W.gdw = take(sizeof(double) * 3 * W.fcap);
+    W.phi = take(rs * (ncells + 1) * g.ns);   // + one row of zeros
     W.loc = take(rs * ncells * g.ns);
-    W.sphi = take(rs * W.fcap);
+    W.sphi = take(sizeof(double) * W.fcap);
     W.sfld = take(rs * 3 * W.fcap);
     W.epart = take(sizeof(double) * W.e_blocks);
     W.total = off;
@@ -317,6 +339,7 @@ int eqfmm_plan_upload(eqfmm_plan *plan, void *dev_buf, size_t bytes, void *strea
     plan->ops.K = b + plan->off_K;
     plan->ops.T = b + plan->off_T;
     plan->ops.Kmx = b + plan->off_Kmx;
+    plan->ops.offs = b + plan->off_offs;
     return EQFMM_OK;
 }
 
