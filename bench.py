@@ -31,6 +31,9 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default=None, help="f64 | f32 | bf16far (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="run one plain device copy of MB megabytes before the timed region "
+                         "(reference kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
@@ -58,6 +61,13 @@ def main():
         dx, dq = plan.backward(qt, one, ws=ws)
         return E, phi, field, dx, dq
 
+    if args.calibrate_copy:
+        src = torch.empty(args.calibrate_copy * 2 ** 20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -131,7 +131,7 @@ void mx_layout_fill(const Geom &g, int precision, const std::vector<double> &K, 
 // matrix cores work on step s.  Each displacement's product goes to a fresh
 // accumulator pair that is added to float running sums when the
 // displacement is complete.
-template <int N, bool BF16, int CH, bool PERIODIC>
+template <int N, bool BF16, int CH, bool PERIODIC, int NSPLIT>
 __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__ Kmx,
                                                 const signed char *__restrict__ offs, int level,
                                                 float inv_side, const float *__restrict__ phi,
@@ -147,11 +147,19 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     const int per = gridDim.x >> 3;
     const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (wg >= nwg) return;
-    const int ntg = (ntile + 3) >> 2;
+    // a workgroup of 4 waves holds TPW = 4 / NSPLIT tiles; NSPLIT waves share
+    // one tile, each running a contiguous part of the interaction list, and
+    // their sums are added in a fixed order at the end
+    constexpr int TPW = 4 / NSPLIT;
+    const int ntg = (ntile + TPW - 1) / TPW;
     const int tg = wg % ntg, pn = wg / ntg;
     const int nb = pn % NB, p = pn / NB;
     const int lane = threadIdx.x & 63;
-    const int t = tg * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const int t = tg * TPW + wv % TPW;
+    const int hs = wv / TPW;
+    constexpr int OPS = (189 + NSPLIT - 1) / NSPLIT;
+    const int o_begin = hs * OPS, o_end = o_begin + OPS < 189 ? o_begin + OPS : 189;
     // the interaction list of this parity, packed (ox+3) | (oy+3) << 4 | (oz+3) << 8
     __shared__ int soff[189];
     if (threadIdx.x < 189) {
@@ -159,7 +167,7 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
         soff[threadIdx.x] = (q[0] + 3) | ((q[1] + 3) << 4) | ((q[2] + 3) << 8);
     }
     __syncthreads();
-    if (t >= ntile) return;
+    const bool active = t < ntile;
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
     const int D = 1 << level, Dp = D >> 1;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
@@ -168,7 +176,6 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     const bool cvalid = Pm < nparent;
     const int cx = 2 * compact3(Pm) + px, cy = 2 * compact3(Pm >> 1) + py, cz = 2 * compact3(Pm >> 2) + pz;
 
-    const int nsteps = 189 * NCH;
     float4 abuf[2][CH];
     using BT = typename std::conditional<BF16, bf16x8, float4>::type;
     constexpr int NBL = BF16 ? CH / 2 : CH;   // B loads per step
@@ -179,7 +186,7 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     // reads a row of zeros.
     auto issue = [&](int step, auto bc) {
         constexpr int b = decltype(bc)::value;
-        step = step < nsteps ? step : nsteps - 1;
+        step = step < o_end * NCH ? step : o_end * NCH - 1;
         const int oidx = step / NCH, ch = step - oidx * NCH;
         const int pk = soff[oidx];
         const int ox = (pk & 15) - 3, oy = ((pk >> 4) & 15) - 3, oz = (pk >> 8) - 3;
@@ -240,26 +247,37 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     // that the register stage of every step is a constant and the body has
     // no branches; the second displacement of the last trip is a clamped
     // repeat whose sum is discarded.
-    issue(0, std::integral_constant<int, 0>{});
-    for (int op = 0; op < 189; op += 2) {
-        static_for<0, 2 * NCH>([&](auto J) {
-            constexpr int j = decltype(J)::value;
-            constexpr int b = j & 1;
-            constexpr int ch = j % NCH;
-            issue(op * NCH + j + 1, std::integral_constant<int, 1 - b>{});
-            // keep the loads of the next step ahead of this step's products
-            __builtin_amdgcn_sched_barrier(0);
-            if constexpr (ch == 0) {
-                c0 = floatx16{};
-                c1 = floatx16{};
-            }
-            compute(std::integral_constant<int, b>{});
-            if constexpr (ch == NCH - 1) {
-                const float keep = op + j / NCH < 189 ? 1.f : 0.f;
-                run += (c0 + c1) * keep;
-            }
-        });
+    if (active) {
+        issue(o_begin * NCH, std::integral_constant<int, 0>{});
+        for (int op = o_begin; op < o_end; op += 2) {
+            static_for<0, 2 * NCH>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                constexpr int b = j & 1;
+                constexpr int ch = j % NCH;
+                issue(op * NCH + j + 1, std::integral_constant<int, 1 - b>{});
+                // keep the loads of the next step ahead of this step's products
+                __builtin_amdgcn_sched_barrier(0);
+                if constexpr (ch == 0) {
+                    c0 = floatx16{};
+                    c1 = floatx16{};
+                }
+                compute(std::integral_constant<int, b>{});
+                if constexpr (ch == NCH - 1) {
+                    const float keep = op + j / NCH < o_end ? 1.f : 0.f;
+                    run += (c0 + c1) * keep;
+                }
+            });
+        }
     }
+    if constexpr (NSPLIT > 1) {
+        __shared__ floatx16 red[NSPLIT - 1][TPW][64];
+        if (hs > 0) red[hs - 1][wv % TPW][lane] = run;
+        __syncthreads();
+        if (hs > 0) return;
+#pragma unroll
+        for (int h = 0; h < NSPLIT - 1; ++h) run += red[h][wv % TPW][lane];
+    }
+    if (!active) return;
 
     // C[cell][node]: lane l, register r -> node j = l % 32, cell
     // ii = 4 (l / 32) + (r % 4) + 8 (r / 4)
@@ -419,22 +437,31 @@ int launch_mx(eqfmm_plan *plan, int level, const float *phi_l, const float *zrow
     const int Dp = (1 << level) >> 1;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
     const int ntile = int((nparent + 31) / 32);
-    const int nwg = 8 * S::NB * ((ntile + 3) / 4);
-    const int grid = (nwg + 7) & ~7;
     const float inv_side = float(double(1 << level) / g.box);
     const signed char *offs = static_cast<const signed char *>(plan->ops.offs);
+    // waves per tile: enough waves to keep every SIMD busy on small levels
+    const int64_t tiles = int64_t(8) * S::NB * ntile;
+    const int split = tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4);
+    const int tpw = 4 / split;
+    const int nwg = 8 * S::NB * ((ntile + tpw - 1) / tpw);
+    const int grid = (nwg + 7) & ~7;
     // bf16 inputs only on the two finest levels, which carry nearly all the
     // work; on coarse levels the cells hold many charges and bf16 rounding of
     // their large, sign-cancelling vectors leaves a spurious net charge
     const bool bf = plan->p.precision == EQFMM_FP32_BF16FAR && level >= g.L - 1;
     const void *Kl = bf ? static_cast<const unsigned char *>(plan->ops.Kmx) + mx_f32_bytes(g) : plan->ops.Kmx;
-#define EQ_M2L_LAUNCH(B, P)                                                                      \
-    k_m2l_mx<N, B, CH, P><<<grid, 256, 0, st>>>(g, Kl, offs, level, inv_side, phi_l, zrow,        \
-                                                loc_l, ntile, nwg)
-    if (bf && g.periodic) EQ_M2L_LAUNCH(true, true);
-    else if (bf) EQ_M2L_LAUNCH(true, false);
-    else if (g.periodic) EQ_M2L_LAUNCH(false, true);
-    else EQ_M2L_LAUNCH(false, false);
+#define EQ_M2L_LAUNCH(B, P, S)                                                                      \
+    k_m2l_mx<N, B, CH, P, S><<<grid, 256, 0, st>>>(g, Kl, offs, level, inv_side, phi_l, zrow,         \
+                                                       loc_l, ntile, nwg)
+#define EQ_M2L_SPLIT(B, P)                            \
+    if (split == 1) EQ_M2L_LAUNCH(B, P, 1);           \
+    else if (split == 2) EQ_M2L_LAUNCH(B, P, 2);      \
+    else EQ_M2L_LAUNCH(B, P, 4);
+    if (bf && g.periodic) { EQ_M2L_SPLIT(true, true) }
+    else if (bf) { EQ_M2L_SPLIT(true, false) }
+    else if (g.periodic) { EQ_M2L_SPLIT(false, true) }
+    else { EQ_M2L_SPLIT(false, false) }
+#undef EQ_M2L_SPLIT
 #undef EQ_M2L_LAUNCH
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
