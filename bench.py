@@ -23,6 +23,22 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 
+def counter_traffic(workload, prec):
+    """HBM bytes per far-field launch from the committed hardware-counter
+    record (profiles/m2l_c2_traffic.json), or None when that record is for
+    another workload or precision or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "m2l_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec["kernel_source"])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != rec["kernel_source_sha256"] or rec["workload"] != workload or prec != 1:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,14 +103,17 @@ def main():
             print(f"[bench]   {k:8s} {v['ms'] / args.steps:8.4f} ms/step  launches/step "
                   f"{v['launches'] / args.steps:.0f}", file=sys.stderr, flush=True)
 
+    # dominant kernel: the far-field products of all levels (one launch per
+    # step; two in the bf16 mode)
     m2l = prof["m2l"]
     peak_key = {eq.FP64: "fp64_mfma", eq.FP32: "fp32_mfma", eq.FP32_BF16FAR: "bf16_mfma"}[prec]
     achieved = m2l["flops"] / (m2l["ms"] * 1e-3) / 1e12 if m2l["ms"] > 0 else 0.0
     roofline = {"kernel": "m2l", "bound": "mfma", "achieved": round(achieved, 3),
                 "peak": PEAKS[peak_key], "unit": "TFLOP/s", "frac": round(achieved / PEAKS[peak_key], 4),
-                "traffic": None,
+                "traffic": counter_traffic(w.name, prec),
                 "avg_launch_ms": round(m2l["ms"] / max(m2l["launches"], 1), 5),
-                "launches_per_step": m2l["launches"] / args.steps}
+                "launches_per_step": m2l["launches"] / args.steps,
+                "algorithmic_flops_per_step": m2l["flops"] / args.steps}
 
     E, phi, field, dx, dq = out
     result = {

@@ -132,7 +132,8 @@ const char *eqfmm_strerror(int code);
  * every launch of a stage is bracketed by events; eqfmm_profile_read
  * synchronises and returns, for `stage` (EQFMM_STAGE_*), the summed kernel
  * time in ms, the number of launches, and the algorithmic flop and byte
- * counts of those launches.  Enabling clears the totals. */
+ * counts of those launches (EQFMM_STAGE_M2L: one launch covers every
+ * interaction level; two in the bf16 mode).  Enabling clears the totals. */
 enum {
     EQFMM_STAGE_BIN = 0, EQFMM_STAGE_P2M = 1, EQFMM_STAGE_M2M = 2, EQFMM_STAGE_M2L = 3,
     EQFMM_STAGE_L2L = 4, EQFMM_STAGE_LEAF = 5, EQFMM_STAGE_GATHER = 6, EQFMM_STAGE_ADJOINT = 7,

@@ -14,6 +14,7 @@ namespace eqfmm {
 constexpr int kMaxOrder = 7;
 constexpr int kMaxPieces = kMaxOrder + 1;   // split pieces along one axis (odd n: n + 1)
 constexpr int kNumOffsets = 343;            // 7^3 displacements between same-level cells
+constexpr int kListLen = 192;               // interaction list (189) padded for the far-field kernels
 
 // Geometry shared by every kernel (passed by value).
 struct Geom {
@@ -35,7 +36,7 @@ struct DevOps {
     const void *K;          // Coulomb matrices [343][n3][n3] at unit cell side
     const void *T;          // periodic root operator [n3][n3] at unit box side
     const void *Kmx;        // matrix-core operand layout of K (precision specific)
-    const void *offs;       // interaction lists per parity: int8 [8][189][3]
+    const void *offs;       // interaction lists per parity: int8 [8][kListLen][3]
 };
 
 // Host plan (the public opaque type).

@@ -483,26 +483,25 @@ __global__ void __launch_bounds__(Ord<N>::TPC) k_l2l(const R *G, int Dl, const R
     for (int o = threadIdx.x; o < 8 * O::NS; o += blockDim.x) {
         const int b = o / O::NS, e = o % O::NS;
         const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+        if (e >= N3) continue;
+        const int i1 = e % N, i2 = (e / N) % N, i3 = e / (N * N);
         R acc = R(0);
-        if (e < N3) {
-            const int i1 = e % N, i2 = (e / N) % N, i3 = e / (N * N);
 #pragma unroll
-            for (int j3 = 0; j3 < N; ++j3)
-                acc += Gs[(bz * N + j3) * N + i3] * uy[(bx + 2 * by) * N3 + i1 + N * i2 + N * N * j3];
-        }
+        for (int j3 = 0; j3 < N; ++j3)
+            acc += Gs[(bz * N + j3) * N + i3] * uy[(bx + 2 * by) * N3 + i1 + N * i2 + N * N * j3];
         const int64_t c = (2 * X + bx) + int64_t(Dl) * ((2 * Y + by) + int64_t(Dl) * (2 * Z + bz));
-        locc[c * O::NS + e] = acc;
+        locc[c * O::NS + e] += acc;
     }
 }
 
-// periodic root: far images of the whole box acting on its own lattice
+// periodic root: far images of the whole box acting on its own lattice (stores L_0)
 template <typename R>
 __global__ void __launch_bounds__(256) k_root(const R *T, int n3, R inv_box, const R *phi0, R *loc0)
 {
     for (int a = threadIdx.x; a < n3; a += blockDim.x) {
         R acc = R(0);
         for (int b = 0; b < n3; ++b) acc += T[a * n3 + b] * phi0[b];
-        loc0[a] += inv_box * acc;
+        loc0[a] = inv_box * acc;
     }
 }
 
@@ -749,7 +748,8 @@ unsigned blocks(int64_t work, int per) { return unsigned((work + per - 1) / per)
 
 // far field at one level (declared here, defined with the matrix-core kernels)
 template <typename R>
-int launch_m2l(eqfmm_plan *plan, int level, const R *phi_l, const R *zrow, R *loc_l, hipStream_t st);
+int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const R *phi, const R *zrow, R *loc,
+               hipStream_t st);
 
 template <int N, typename R>
 int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi_out,
@@ -819,30 +819,24 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     }
     prof_end(plan, st, pk, EQFMM_STAGE_M2M, 0.0, 0.0);
 
-    // a5/a6: downward pass
-    const int64_t ncells_all = W.lvl[L + 1];
+    // a5/a6: downward pass.  The far-field products of every interaction
+    // level are computed in one launch, each storing its level's local
+    // vectors; the shifts then add each parent's functional into its
+    // children, top down (Psi_child = Psi_parent o shift + far terms).
     if (g.periodic) {
-        EQ_CHECK(hipMemsetAsync(v.loc, 0, O::NS * rs, st));
         k_root<R><<<1, 256, 0, st>>>(static_cast<const R *>(ops.T), O::N3, R(1.0 / g.box), v.phi, v.loc);
         EQ_CHECK(hipGetLastError());
-    } else {
-        // levels 0..2 start from zero (Psi vanishes at levels 0 and 1)
-        EQ_CHECK(hipMemsetAsync(v.loc, 0, W.lvl[3] * O::NS * rs, st));
     }
-    (void)ncells_all;
-    for (int l = lmin; l <= L; ++l) {
-        const int Dl = 1 << l;
-        if (l > 2 || g.periodic) {
-            pk = prof_begin(plan, st);
-            const int64_t np = int64_t(1) << (3 * (l - 1));
-            k_l2l<N, R><<<dim3(unsigned(np)), O::TPC, 0, st>>>(G, Dl, v.loc + W.lvl[l - 1] * O::NS,
-                                                               v.loc + W.lvl[l] * O::NS);
-            EQ_CHECK(hipGetLastError());
-            prof_end(plan, st, pk, EQFMM_STAGE_L2L, 0.0, 0.0);
-        }
-        rc = launch_m2l<R>(plan, l, v.phi + W.lvl[l] * O::NS, v.phi + W.lvl[L + 1] * O::NS,
-                           v.loc + W.lvl[l] * O::NS, st);
-        if (rc) return rc;
+    rc = launch_m2l<R>(plan, lmin, L, W.lvl.data(), v.phi, v.phi + W.lvl[L + 1] * O::NS, v.loc, st);
+    if (rc) return rc;
+    // free space: Psi vanishes at levels 0 and 1, so the shifts start at 2 -> 3
+    for (int l = g.periodic ? 1 : 3; l <= L; ++l) {
+        pk = prof_begin(plan, st);
+        const int64_t np = int64_t(1) << (3 * (l - 1));
+        k_l2l<N, R><<<dim3(unsigned(np)), O::TPC, 0, st>>>(G, 1 << l, v.loc + W.lvl[l - 1] * O::NS,
+                                                           v.loc + W.lvl[l] * O::NS);
+        EQ_CHECK(hipGetLastError());
+        prof_end(plan, st, pk, EQFMM_STAGE_L2L, 0.0, 0.0);
     }
 
     // a7/a8: far field at the fragments and the near field

@@ -4,7 +4,7 @@
 // Work decomposition: every target cell with the same parity p (cell index
 // mod 2 per axis) has the same interaction list, the 189 displacements o in
 // [-2-p, 3-p]^3 minus the 27 adjacent ones (children of the parent's
-// neighbours that are not adjacent).  A wave owns 32 target cells of one
+// neighbours that are not adjacent), padded to kListLen with zero matrices.  A wave owns 32 target cells of one
 // parity (the same child of 32 parents that are consecutive in Morton order,
 // a 4x4x2 block) and one 32-wide block of target nodes, and runs through the
 // interaction list; for each displacement the 32 source rows form the A
@@ -29,6 +29,16 @@ namespace eqfmm {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// The interaction levels of one evaluation, handled by a single launch:
+// workgroups [wg_begin[i], wg_begin[i+1]) belong to level level[i].
+struct MxLevels {
+    int nlev;
+    int level[8], ntile[8], wg_begin[9];
+    int64_t cell0[8];      // first cell of the level in the Phi / L arrays
+    float inv_side[8];
+    double inv_side64[8];
+};
 
 template <int N> struct MxShape {
     static constexpr int N3 = N * N * N;
@@ -133,10 +143,10 @@ void mx_layout_fill(const Geom &g, int precision, const std::vector<double> &K, 
 // displacement is complete.
 template <int N, bool BF16, int CH, bool PERIODIC, int NSPLIT>
 __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__ Kmx,
-                                                const signed char *__restrict__ offs, int level,
-                                                float inv_side, const float *__restrict__ phi,
+                                                const signed char *__restrict__ offs, MxLevels lv,
+                                                const float *__restrict__ phi_all,
                                                 const float *__restrict__ zrow,
-                                                float *__restrict__ loc, int ntile, int nwg)
+                                                float *__restrict__ loc_all, int nwg)
 {
     using S = MxShape<N>;
     constexpr int NS = S::NS, KH = S::KH, NB = S::NB;
@@ -145,8 +155,15 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     static_assert(NA % CH == 0, "chunking");
     static_assert(!BF16 || CH % 2 == 0, "bf16 steps take 8 sources per lane");
     const int per = gridDim.x >> 3;
-    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (wg >= nwg) return;
+    int li = 0;
+    while (li + 1 < lv.nlev && wg >= lv.wg_begin[li + 1]) ++li;
+    wg -= lv.wg_begin[li];
+    const int level = lv.level[li], ntile = lv.ntile[li];
+    const float inv_side = lv.inv_side[li];
+    const float *phi = phi_all + lv.cell0[li] * NS;
+    float *loc = loc_all + lv.cell0[li] * NS;
     // a workgroup of 4 waves holds TPW = 4 / NSPLIT tiles; NSPLIT waves share
     // one tile, each running a contiguous part of the interaction list, and
     // their sums are added in a fixed order at the end
@@ -158,12 +175,13 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     const int wv = threadIdx.x >> 6;
     const int t = tg * TPW + wv % TPW;
     const int hs = wv / TPW;
-    constexpr int OPS = (189 + NSPLIT - 1) / NSPLIT;
-    const int o_begin = hs * OPS, o_end = o_begin + OPS < 189 ? o_begin + OPS : 189;
+    constexpr int OPS = kListLen / NSPLIT;           // even: displacements go in pairs
+    static_assert(kListLen % (2 * NSPLIT) == 0, "list padding");
+    const int o_begin = hs * OPS, o_end = o_begin + OPS;
     // the interaction list of this parity, packed (ox+3) | (oy+3) << 4 | (oz+3) << 8
-    __shared__ int soff[189];
-    if (threadIdx.x < 189) {
-        const signed char *q = offs + (p * 189 + threadIdx.x) * 3;
+    __shared__ int soff[kListLen];
+    if (threadIdx.x < kListLen) {
+        const signed char *q = offs + (p * kListLen + threadIdx.x) * 3;
         soff[threadIdx.x] = (q[0] + 3) | ((q[1] + 3) << 4) | ((q[2] + 3) << 8);
     }
     __syncthreads();
@@ -186,7 +204,7 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     // reads a row of zeros.
     auto issue = [&](int step, auto bc) {
         constexpr int b = decltype(bc)::value;
-        step = step < o_end * NCH ? step : o_end * NCH - 1;
+        step = step < o_end * NCH ? step : o_end * NCH - 1;   // prefetch past the end
         const int oidx = step / NCH, ch = step - oidx * NCH;
         const int pk = soff[oidx];
         const int ox = (pk & 15) - 3, oy = ((pk >> 4) & 15) - 3, oz = (pk >> 8) - 3;
@@ -262,10 +280,7 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
                     c1 = floatx16{};
                 }
                 compute(std::integral_constant<int, b>{});
-                if constexpr (ch == NCH - 1) {
-                    const float keep = op + j / NCH < o_end ? 1.f : 0.f;
-                    run += (c0 + c1) * keep;
-                }
+                if constexpr (ch == NCH - 1) run += c0 + c1;
             });
         }
     }
@@ -290,7 +305,7 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
         if (P2 >= nparent) continue;
         const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
         const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
-        loc[c * NS + j] += inv_side * run[r];
+        loc[c * NS + j] = inv_side * run[r];
     }
 }
 
@@ -302,26 +317,33 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // quarter wave.  Same pipelining as the float kernel.
 template <int N, int CH, bool PERIODIC>
 __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restrict__ Kmx,
-                                                 const signed char *__restrict__ offs, int level,
-                                                 double inv_side, const double *__restrict__ phi,
+                                                 const signed char *__restrict__ offs, MxLevels lv,
+                                                 const double *__restrict__ phi_all,
                                                  const double *__restrict__ zrow,
-                                                 double *__restrict__ loc, int ntile, int nwg)
+                                                 double *__restrict__ loc_all, int nwg)
 {
     constexpr int N3 = N * N * N, NS = (N3 + 15) & ~15, KQ = NS / 4, NB = (N3 + 15) / 16;
     constexpr int NA = KQ / 2;            // double2 loads of one quarter row
     constexpr int NCH = NA / CH;
     static_assert(NA % CH == 0, "chunking");
     const int per = gridDim.x >> 3;
-    const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (wg >= nwg) return;
+    int li = 0;
+    while (li + 1 < lv.nlev && wg >= lv.wg_begin[li + 1]) ++li;
+    wg -= lv.wg_begin[li];
+    const int level = lv.level[li], ntile = lv.ntile[li];
+    const double inv_side = lv.inv_side64[li];
+    const double *phi = phi_all + lv.cell0[li] * NS;
+    double *loc = loc_all + lv.cell0[li] * NS;
     const int ntg = (ntile + 3) >> 2;
     const int tg = wg % ntg, pn = wg / ntg;
     const int nb = pn % NB, p = pn / NB;
     const int lane = threadIdx.x & 63;
     const int t = tg * 4 + (threadIdx.x >> 6);
-    __shared__ int soff[189];
-    if (threadIdx.x < 189) {
-        const signed char *q = offs + (p * 189 + threadIdx.x) * 3;
+    __shared__ int soff[kListLen];
+    if (threadIdx.x < kListLen) {
+        const signed char *q = offs + (p * kListLen + threadIdx.x) * 3;
         soff[threadIdx.x] = (q[0] + 3) | ((q[1] + 3) << 4) | ((q[2] + 3) << 8);
     }
     __syncthreads();
@@ -337,7 +359,7 @@ __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restri
 
     auto issue = [&](int step, auto bc) {
         constexpr int b = decltype(bc)::value;
-        constexpr int nsteps = 189 * NCH;
+        constexpr int nsteps = kListLen * NCH;
         step = step < nsteps ? step : nsteps - 1;
         const int oidx = step / NCH, ch = step - oidx * NCH;
         const int pk = soff[oidx];
@@ -363,7 +385,7 @@ __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restri
 
     doublex4 c0 = {}, c1 = {}, run = {};
     issue(0, std::integral_constant<int, 0>{});
-    for (int op = 0; op < 189; op += 2) {
+    for (int op = 0; op < kListLen; op += 2) {
         static_for<0, 2 * NCH>([&](auto J) {
             constexpr int j = decltype(J)::value;
             constexpr int b = j & 1;
@@ -379,10 +401,7 @@ __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restri
                 c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[b][c].x, bbuf[b][c].x, c0, 0, 0, 0);
                 c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[b][c].y, bbuf[b][c].y, c1, 0, 0, 0);
             }
-            if constexpr (ch == NCH - 1) {
-                const double keep = op + j / NCH < 189 ? 1.0 : 0.0;
-                run += (c0 + c1) * keep;
-            }
+            if constexpr (ch == NCH - 1) run += c0 + c1;
         });
     }
     // lane l, register r -> node j = l % 16, cell ii = l / 16 + 4 r
@@ -395,7 +414,7 @@ __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restri
         if (P2 >= nparent) continue;
         const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
         const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
-        loc[c * NS + j] += inv_side * run[r];
+        loc[c * NS + j] = inv_side * run[r];
     }
 }
 
@@ -422,124 +441,137 @@ double il_pairs(const Geom &g, int level)
     return double(A) * A * A - double(B) * B * B;
 }
 
+// Level table: tiles of `cells_per_tile` parents per (parity, node block),
+// `tpw` tiles per workgroup.
+int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, int cells_per_tile, int nb, int tpw,
+                MxLevels &lv)
+{
+    lv.nlev = lmax - lmin + 1;
+    int wgs = 0;
+    for (int i = 0; i < lv.nlev; ++i) {
+        const int l = lmin + i;
+        const int Dp = (1 << l) >> 1;
+        const int64_t nparent = int64_t(Dp) * Dp * Dp;
+        lv.level[i] = l;
+        lv.ntile[i] = int((nparent + cells_per_tile - 1) / cells_per_tile);
+        lv.wg_begin[i] = wgs;
+        wgs += 8 * nb * ((lv.ntile[i] + tpw - 1) / tpw);
+        lv.cell0[i] = lvl[l];
+        lv.inv_side[i] = float(double(1 << l) / g.box);
+        lv.inv_side64[i] = double(1 << l) / g.box;
+    }
+    lv.wg_begin[lv.nlev] = wgs;
+    return wgs;
+}
+
+// k-chunk per pipeline step: four float4 loads of A and of B per lane (a
+// larger chunk doubles the register stages and halves the resident waves)
 template <int N> struct MxChunk {
     static constexpr int NA = MxShape<N>::KH / 4;
-    static constexpr int CH = NA % 8 == 0 ? 8 : (NA % 4 == 0 ? 4 : NA);
+    static constexpr int CH = NA % 4 == 0 ? 4 : NA;
 };
 
 template <int N>
-int launch_mx(eqfmm_plan *plan, int level, const float *phi_l, const float *zrow, float *loc_l,
-              hipStream_t st)
+int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const float *phi, const float *zrow,
+              float *loc, hipStream_t st)
 {
     using S = MxShape<N>;
     constexpr int CH = MxChunk<N>::CH;
     const Geom &g = plan->g;
-    const int Dp = (1 << level) >> 1;
-    const int64_t nparent = int64_t(Dp) * Dp * Dp;
-    const int ntile = int((nparent + 31) / 32);
-    const float inv_side = float(double(1 << level) / g.box);
     const signed char *offs = static_cast<const signed char *>(plan->ops.offs);
-    // waves per tile: enough waves to keep every SIMD busy on small levels
-    const int64_t tiles = int64_t(8) * S::NB * ntile;
+    // waves per tile: enough waves to keep every SIMD busy
+    int64_t tiles = 0;
+    for (int l = lmin; l <= lmax; ++l) {
+        const int64_t Dp = (int64_t(1) << l) >> 1;
+        tiles += 8 * S::NB * ((Dp * Dp * Dp + 31) / 32);
+    }
     const int split = tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4);
-    const int tpw = 4 / split;
-    const int nwg = 8 * S::NB * ((ntile + tpw - 1) / tpw);
-    const int grid = (nwg + 7) & ~7;
     // bf16 inputs only on the two finest levels, which carry nearly all the
     // work; on coarse levels the cells hold many charges and bf16 rounding of
     // their large, sign-cancelling vectors leaves a spurious net charge
-    const bool bf = plan->p.precision == EQFMM_FP32_BF16FAR && level >= g.L - 1;
-    const void *Kl = bf ? static_cast<const unsigned char *>(plan->ops.Kmx) + mx_f32_bytes(g) : plan->ops.Kmx;
-#define EQ_M2L_LAUNCH(B, P, S)                                                                      \
-    k_m2l_mx<N, B, CH, P, S><<<grid, 256, 0, st>>>(g, Kl, offs, level, inv_side, phi_l, zrow,         \
-                                                       loc_l, ntile, nwg)
-#define EQ_M2L_SPLIT(B, P)                            \
-    if (split == 1) EQ_M2L_LAUNCH(B, P, 1);           \
-    else if (split == 2) EQ_M2L_LAUNCH(B, P, 2);      \
+    const bool bf = plan->p.precision == EQFMM_FP32_BF16FAR;
+    const void *Kbf = static_cast<const unsigned char *>(plan->ops.Kmx) + mx_f32_bytes(g);
+    auto go = [&](int l0, int l1, bool use_bf) -> int {
+        if (l0 > l1) return EQFMM_OK;
+        MxLevels lv;
+        const int nwg = fill_levels(g, l0, l1, lvl, 32, S::NB, 4 / split, lv);
+        const int grid = (nwg + 7) & ~7;
+        const void *K = use_bf ? Kbf : plan->ops.Kmx;
+#define EQ_M2L_LAUNCH(B, P, SP) \
+    k_m2l_mx<N, B, CH, P, SP><<<grid, 256, 0, st>>>(g, K, offs, lv, phi, zrow, loc, nwg)
+#define EQ_M2L_SPLIT(B, P)                           \
+    if (split == 1) EQ_M2L_LAUNCH(B, P, 1);          \
+    else if (split == 2) EQ_M2L_LAUNCH(B, P, 2);     \
     else EQ_M2L_LAUNCH(B, P, 4);
-    if (bf && g.periodic) { EQ_M2L_SPLIT(true, true) }
-    else if (bf) { EQ_M2L_SPLIT(true, false) }
-    else if (g.periodic) { EQ_M2L_SPLIT(false, true) }
-    else { EQ_M2L_SPLIT(false, false) }
+        if (use_bf && g.periodic) { EQ_M2L_SPLIT(true, true) }
+        else if (use_bf) { EQ_M2L_SPLIT(true, false) }
+        else if (g.periodic) { EQ_M2L_SPLIT(false, true) }
+        else { EQ_M2L_SPLIT(false, false) }
 #undef EQ_M2L_SPLIT
 #undef EQ_M2L_LAUNCH
-    return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+        return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+    };
+    if (!bf) return go(lmin, lmax, false);
+    const int lb = lmax - 1 > lmin ? lmax - 1 : lmin;
+    const int rc = go(lmin, lb - 1, false);
+    return rc ? rc : go(lb, lmax, true);
 }
-
-}  // namespace
-
-template <typename R>
-int launch_m2l(eqfmm_plan *plan, int level, const R *phi_l, const R *zrow, R *loc_l, hipStream_t st);
-
-template <>
-int launch_m2l<float>(eqfmm_plan *plan, int level, const float *phi_l, const float *zrow, float *loc_l,
-                      hipStream_t st)
-{
-    const Geom &g = plan->g;
-    const int pk = prof_begin_m2l(plan, st);
-    int rc;
-    switch (g.n) {
-        case 2: rc = launch_mx<2>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 3: rc = launch_mx<3>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 4: rc = launch_mx<4>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 5: rc = launch_mx<5>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 6: rc = launch_mx<6>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 7: rc = launch_mx<7>(plan, level, phi_l, zrow, loc_l, st); break;
-        default: rc = EQFMM_EINVAL;
-    }
-    const int64_t ncell = int64_t(1) << (3 * level);
-    prof_end_m2l(plan, st, pk, 2.0 * double(g.n3) * g.n3 * il_pairs(g, level),
-                 double(ncell) * g.ns * sizeof(float) * 3.0);
-    return rc;
-}
-
-namespace {
 
 template <int N>
-int launch_f64(eqfmm_plan *plan, int level, const double *phi_l, const double *zrow, double *loc_l,
-               hipStream_t st)
+int launch_f64(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const double *phi, const double *zrow,
+               double *loc, hipStream_t st)
 {
     constexpr int NA = ((N * N * N + 15) & ~15) / 8;
     constexpr int CH = NA % 4 == 0 ? 4 : (NA % 2 == 0 ? 2 : 1);
     constexpr int NB = (N * N * N + 15) / 16;
     const Geom &g = plan->g;
-    const int Dp = (1 << level) >> 1;
-    const int64_t nparent = int64_t(Dp) * Dp * Dp;
-    const int ntile = int((nparent + 15) / 16);
-    const int nwg = 8 * NB * ((ntile + 3) / 4);
+    MxLevels lv;
+    const int nwg = fill_levels(g, lmin, lmax, lvl, 16, NB, 4, lv);
     const int grid = (nwg + 7) & ~7;
-    const double inv_side = double(1 << level) / g.box;
     const double2 *K = static_cast<const double2 *>(plan->ops.Kmx);
     const signed char *offs = static_cast<const signed char *>(plan->ops.offs);
     if (g.periodic)
-        k_m2l_f64<N, CH, true><<<grid, 256, 0, st>>>(g, K, offs, level, inv_side, phi_l, zrow, loc_l, ntile, nwg);
+        k_m2l_f64<N, CH, true><<<grid, 256, 0, st>>>(g, K, offs, lv, phi, zrow, loc, nwg);
     else
-        k_m2l_f64<N, CH, false><<<grid, 256, 0, st>>>(g, K, offs, level, inv_side, phi_l, zrow, loc_l, ntile, nwg);
+        k_m2l_f64<N, CH, false><<<grid, 256, 0, st>>>(g, K, offs, lv, phi, zrow, loc, nwg);
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
 
 }  // namespace
 
-template <>
-int launch_m2l<double>(eqfmm_plan *plan, int level, const double *phi_l, const double *zrow,
-                       double *loc_l, hipStream_t st)
+// All interaction levels lmin..lmax in one launch (two for the bf16 mode);
+// each writes (stores) its level's local vectors.
+template <typename R>
+int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const R *phi, const R *zrow, R *loc,
+               hipStream_t st)
 {
     const Geom &g = plan->g;
     const int pk = prof_begin_m2l(plan, st);
-    int rc;
+    int rc = EQFMM_EINVAL;
+#define EQ_CASE(NN)                                                                          \
+    case NN:                                                                                 \
+        if constexpr (sizeof(R) == sizeof(float))                                            \
+            rc = launch_mx<NN>(plan, lmin, lmax, lvl, phi, zrow, loc, st);                   \
+        else                                                                                 \
+            rc = launch_f64<NN>(plan, lmin, lmax, lvl, phi, zrow, loc, st);                  \
+        break;
     switch (g.n) {
-        case 2: rc = launch_f64<2>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 3: rc = launch_f64<3>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 4: rc = launch_f64<4>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 5: rc = launch_f64<5>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 6: rc = launch_f64<6>(plan, level, phi_l, zrow, loc_l, st); break;
-        case 7: rc = launch_f64<7>(plan, level, phi_l, zrow, loc_l, st); break;
-        default: rc = EQFMM_EINVAL;
+        EQ_CASE(2) EQ_CASE(3) EQ_CASE(4) EQ_CASE(5) EQ_CASE(6) EQ_CASE(7)
+        default: break;
     }
-    const int64_t ncell = int64_t(1) << (3 * level);
-    prof_end_m2l(plan, st, pk, 2.0 * double(g.n3) * g.n3 * il_pairs(g, level),
-                 double(ncell) * g.ns * sizeof(double) * 3.0);
+#undef EQ_CASE
+    double flops = 0.0, bytes = 0.0;
+    for (int l = lmin; l <= lmax; ++l) {
+        flops += 2.0 * double(g.n3) * g.n3 * il_pairs(g, l);
+        bytes += double(int64_t(1) << (3 * l)) * g.ns * sizeof(R) * 2.0;
+    }
+    prof_end_m2l(plan, st, pk, flops, bytes);
     return rc;
 }
+
+template int launch_m2l<float>(eqfmm_plan *, int, int, const int64_t *, const float *, const float *, float *,
+                               hipStream_t);
+template int launch_m2l<double>(eqfmm_plan *, int, int, const int64_t *, const double *, const double *,
+                                double *, hipStream_t);
 
 }  // namespace eqfmm

@@ -165,24 +165,32 @@ int build_image(eqfmm_plan *plan)
     plan->off_K = take(rs * h.K.size());
     plan->off_T = take(rs * std::max<size_t>(h.T.size(), 1));
     plan->off_Kmx = take(std::max<size_t>(mx_layout_bytes(g, prec), 1));
-    plan->off_offs = take(8 * 189 * 3);
+    plan->off_offs = take(8 * kListLen * 3);
     plan->image.assign(off, 0);
     // interaction list of a cell with parity p (cell index mod 2 per axis):
-    // displacements in [-2-p, 3-p]^3 that are not adjacent
+    // displacements in [-2-p, 3-p]^3 that are not adjacent.  The list is
+    // ordered by the parity of the displacement: all targets of one parity
+    // then read sources of a single parity class for ~24 consecutive
+    // displacements, a set that stays in L2.  The 189 entries are padded to
+    // kListLen with the displacement (0,0,0), whose matrix is zero.
     {
         signed char *o = reinterpret_cast<signed char *>(plan->image.data() + plan->off_offs);
         for (int p = 0; p < 8; ++p) {
             const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
             int m = 0;
-            for (int oz = -2 - pz; oz <= 3 - pz; ++oz)
-                for (int oy = -2 - py; oy <= 3 - py; ++oy)
-                    for (int ox = -2 - px; ox <= 3 - px; ++ox) {
-                        if (std::abs(ox) <= 1 && std::abs(oy) <= 1 && std::abs(oz) <= 1) continue;
-                        o[(p * 189 + m) * 3 + 0] = static_cast<signed char>(ox);
-                        o[(p * 189 + m) * 3 + 1] = static_cast<signed char>(oy);
-                        o[(p * 189 + m) * 3 + 2] = static_cast<signed char>(oz);
-                        ++m;
-                    }
+            for (int q = 0; q < 8; ++q)
+                for (int oz = -2 - pz; oz <= 3 - pz; ++oz)
+                    for (int oy = -2 - py; oy <= 3 - py; ++oy)
+                        for (int ox = -2 - px; ox <= 3 - px; ++ox) {
+                            if (std::abs(ox) <= 1 && std::abs(oy) <= 1 && std::abs(oz) <= 1) continue;
+                            if (((ox & 1) | ((oy & 1) << 1) | ((oz & 1) << 2)) != q) continue;
+                            o[(p * kListLen + m) * 3 + 0] = static_cast<signed char>(ox);
+                            o[(p * kListLen + m) * 3 + 1] = static_cast<signed char>(oy);
+                            o[(p * kListLen + m) * 3 + 2] = static_cast<signed char>(oz);
+                            ++m;
+                        }
+            for (; m < kListLen; ++m) o[(p * kListLen + m) * 3 + 0] = o[(p * kListLen + m) * 3 + 1] =
+                                          o[(p * kListLen + m) * 3 + 2] = 0;
         }
     }
     auto &img = plan->image;

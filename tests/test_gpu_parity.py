@@ -63,7 +63,7 @@ CASES = [
     ("c3", 16384, 3, 5, PER_C, 0.0),
     ("c3", 8000, 3, 5, PER, 0.0),
     ("c4", 8192, 3, 6, FREE_C, 0.0),
-    ("c5", 3 * 16 ** 3, 4, 4, PER_C, 0.0),
+    ("c5", 12 * 10 ** 3, 4, 4, PER_C, 0.0),
     ("c1", 3000, 2, 7, FREE, 0.0),
     ("c1", 3000, 3, 2, FREE_C, 0.004),
 ]

@@ -46,7 +46,7 @@ WORKLOADS = {
                    PERIODIC_CONTINUOUS, FP32, 3, "uniform_pm"),
     "c4": Workload("c4-clustered1048576-l6-n6-free-continuous-f32", 1048576, 6, 6,
                    FREE_CONTINUOUS, FP32, 4, "clustered"),
-    "c5": Workload("c5-water3145728-l7-n4-periodic-continuous-f32", 3 * 128 ** 3, 7, 4,
+    "c5": Workload("c5-water3145728-l7-n4-periodic-continuous-f32", 3 * 4 * 64 ** 3, 7, 4,
                    PERIODIC_CONTINUOUS, FP32, 5, "water"),
     "t1": Workload("paper-table1-uniform23040-l3", 23040, 3, 4, FREE, FP64, 11, "uniform_pm"),
 }
@@ -81,21 +81,27 @@ def clustered_positions(rng, n, centres=64, sigma=0.02):
 
 
 # Water-like box: rigid 3-site molecules, O-H 0.09572 nm and H-O-H 104.52
-# degrees, box side = m * 0.3104 nm (liquid-water spacing), scaled to 1.
+# degrees, at the number density of liquid water (one molecule per
+# (0.3104 nm)^3); the box side is scaled to 1.  The oxygens sit on a jittered
+# face-centred cubic lattice of m^3 cells (4 m^3 molecules, 2^20 for m = 64).
 WATER_Q = (-0.834, 0.417, 0.417)
 WATER_SPACING_NM = 0.3104
 WATER_ROH_NM = 0.09572
 WATER_THETA_DEG = 104.52
+FCC_BASIS = ((0.0, 0.0, 0.0), (0.5, 0.5, 0.0), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5))
 
 
 def water_positions(rng, m):
-    """m**3 molecules, O on a jittered cubic lattice, uniform random
-    orientations (unit quaternions); returns [3*m**3, 3] in [0,1) and charges."""
-    r_oh = WATER_ROH_NM / (m * WATER_SPACING_NM)
-    g = (np.arange(m) + 0.5) / m
-    ox, oy, oz = np.meshgrid(g, g, g, indexing="ij")
-    o = np.stack([ox.ravel(), oy.ravel(), oz.ravel()], axis=1)
-    o = o + rng.uniform(-0.1 / m, 0.1 / m, o.shape)
+    """4*m**3 molecules on a jittered FCC lattice of m**3 cells, uniform random
+    orientations (unit quaternions); returns [3*4*m**3, 3] in [0,1) and charges."""
+    nmol = 4 * m ** 3
+    box_nm = WATER_SPACING_NM * nmol ** (1.0 / 3.0)
+    r_oh = WATER_ROH_NM / box_nm
+    g = np.arange(m)
+    cx, cy, cz = np.meshgrid(g, g, g, indexing="ij")
+    cells = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1).astype(float)
+    o = (cells[:, None, :] + np.array(FCC_BASIS)[None, :, :] + 0.25).reshape(-1, 3) / m
+    o = o + rng.uniform(-0.05 / m, 0.05 / m, o.shape)
     nm = o.shape[0]
     # uniform random rotations from unit quaternions (Shoemake's method)
     u1, u2, u3 = rng.random((3, nm))
@@ -144,9 +150,9 @@ def make_inputs(kind, n, seed):
         pos = clustered_positions(rng, n)
         return pos, meansub_charges(rng, n)
     if kind == "water":
-        m = round((n // 3) ** (1.0 / 3.0))
-        if 3 * m ** 3 != n:
-            raise ValueError("water workload needs n = 3*m**3")
+        m = round((n // 12) ** (1.0 / 3.0))
+        if 12 * m ** 3 != n:
+            raise ValueError("water workload needs n = 12*m**3 (FCC cells of 4 molecules)")
         return water_positions(rng, m)
     raise ValueError(f"unknown generator {kind!r}")
 
@@ -163,7 +169,7 @@ def small_variant(key, n, levels, seed_offset=100):
     w = WORKLOADS[key]
     kind = w.kind
     if kind == "water":
-        m = max(2, round((n // 3) ** (1.0 / 3.0)))
-        n = 3 * m ** 3
+        m = max(2, round((n // 12) ** (1.0 / 3.0)))
+        n = 12 * m ** 3
     pos, q = make_inputs(kind, n, w.seed + seed_offset)
     return dataclasses.replace(w, n=n, levels=levels, name=w.name + f"-small{n}-l{levels}"), pos, q
