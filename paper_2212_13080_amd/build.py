@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/plan.cpp", "csrc/kernels.hip", "csrc/m2l.hip"]
+SOURCES = ["csrc/plan.cpp", "csrc/kernels.hip", "csrc/m2l.hip", "csrc/near.hip"]
 LIB = os.path.join(HERE, "libeqfmm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

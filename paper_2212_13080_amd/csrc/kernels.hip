@@ -505,117 +505,6 @@ __global__ void __launch_bounds__(256) k_root(const R *T, int n3, R inv_box, con
     }
 }
 
-// ----------------------------------------------- a7 + a8: L2P and near field
-
-template <typename R> __device__ __forceinline__ R rsq(R x);
-template <> __device__ __forceinline__ double rsq<double>(double x) { return 1.0 / sqrt(x); }
-template <> __device__ __forceinline__ float rsq<float>(float x) { return rsqrtf(x); }
-
-// One target fragment: far field from the finest cell's local vector, near
-// field over the same and 26 adjacent cells.  Storage type R, arithmetic C.
-template <int N, typename C, typename R>
-__device__ __forceinline__ void leaf_target(const Geom &g, const R *t_, const R *den_, int64_t p,
-                                            const int *leafstart, const double *su, const double *sv,
-                                            const double *sw, const R *sq, const int *spar,
-                                            const int *sleaf, const R *locL, double *sphi, R *sfld)
-{
-    using O = Ord<N>;
-    C t[N], den[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        t[k] = C(t_[k]);
-        den[k] = C(den_[k]);
-    }
-    const int leaf = sleaf[p];
-    const int D = g.D;
-    const int cx = leaf % D, cy = (leaf / D) % D, cz = leaf / (D * D);
-    const double ud = su[p], vd = sv[p], wd = sw[p];
-    const C u = C(ud), v = C(vd), w = C(wd);
-    const int par = spar[p];
-    const C s = C(g.s_leaf), inv_s = C(1) / s;
-    const double sd = g.s_leaf;
-    // far field: Psi_leaf evaluated on the replacement of a unit charge here
-    C gx[N], gy[N], gz[N], dx[N], dy[N], dz[N];
-    lag_vals_der<N>(t, den, u, gx, dx);
-    lag_vals_der<N>(t, den, v, gy, dy);
-    lag_vals_der<N>(t, den, w, gz, dz);
-    const R *Lc = locL + int64_t(leaf) * O::NS;
-    C ph = C(0), f0 = C(0), f1 = C(0), f2 = C(0);
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            C s0 = C(0), s1 = C(0);
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const C l = C(Lc[i + N * j + N * N * k]);
-                s0 += gx[i] * l;
-                s1 += dx[i] * l;
-            }
-            ph += gz[k] * gy[j] * s0;
-            f0 += gz[k] * gy[j] * s1;
-            f1 += gz[k] * dy[j] * s0;
-            f2 += dz[k] * gy[j] * s0;
-        }
-    f0 *= -inv_s;
-    f1 *= -inv_s;
-    f2 *= -inv_s;
-    // near field: the same and the 26 adjacent finest cells; fragments of
-    // the same charge do not interact
-    for (int ddz = -1; ddz <= 1; ++ddz)
-        for (int ddy = -1; ddy <= 1; ++ddy)
-            for (int ddx = -1; ddx <= 1; ++ddx) {
-                int nx = cx + ddx, ny = cy + ddy, nz = cz + ddz;
-                if (g.periodic) {
-                    nx = (nx + D) % D;
-                    ny = (ny + D) % D;
-                    nz = (nz + D) % D;
-                } else if (nx < 0 || ny < 0 || nz < 0 || nx >= D || ny >= D || nz >= D) {
-                    continue;
-                }
-                const int nb = nx + D * (ny + D * nz);
-                const int j0 = leafstart[nb], j1 = leafstart[nb + 1];
-                // displacements are formed from the double cell-local
-                // coordinates: float coordinates would limit close pairs
-                // to ~1e-8 * side / r relative accuracy
-                const double ox = ud - ddx, oy = vd - ddy, oz = wd - ddz;
-                for (int j = j0; j < j1; ++j) {
-                    if (spar[j] == par) continue;
-                    const C ex = C((ox - su[j]) * sd), ey = C((oy - sv[j]) * sd), ez = C((oz - sw[j]) * sd);
-                    const C r2 = ex * ex + ey * ey + ez * ez;
-                    const C ri = rsq<C>(r2);
-                    const C qr = C(sq[j]) * ri;
-                    const C qr3 = qr * ri * ri;
-                    ph += qr;
-                    f0 += qr3 * ex;
-                    f1 += qr3 * ey;
-                    f2 += qr3 * ez;
-                }
-            }
-    sphi[p] = double(ph);
-    sfld[3 * p + 0] = R(f0);
-    sfld[3 * p + 1] = R(f1);
-    sfld[3 * p + 2] = R(f2);
-}
-
-// Fragments of split charges are evaluated in double even in the float
-// modes: the force along a split axis is sum_m dw_m phi(p_m) with dw of
-// order 1/(2d), which amplifies float rounding in phi by about s/(2d).
-template <int N, typename R>
-__global__ void __launch_bounds__(256) k_leaf(Geom g, const R *t_, const R *den_, int64_t nfrag,
-                                              const int *leafstart, const double *su, const double *sv,
-                                              const double *sw, const R *sq, const int *spar,
-                                              const int *sleaf, const unsigned char *smask,
-                                              const R *locL, double *sphi, R *sfld)
-{
-    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p >= nfrag) return;
-    if (sizeof(R) == sizeof(float) && g.continuous && smask[spar[p]])
-        leaf_target<N, double>(g, t_, den_, p, leafstart, su, sv, sw, sq, spar, sleaf, locL, sphi, sfld);
-    else
-        leaf_target<N, R>(g, t_, den_, p, leafstart, su, sv, sw, sq, spar, sleaf, locL, sphi, sfld);
-}
-
 // -------------------------------------------------- a9 + a10: gather, energy
 
 template <typename R>
@@ -746,6 +635,13 @@ unsigned blocks(int64_t work, int per) { return unsigned((work + per - 1) / per)
 
 }  // namespace
 
+// far field at the charges and near field (near.hip)
+template <int N, typename R>
+int launch_near(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const int *leafstart,
+                const double *su, const double *sv, const double *sw, const R *sq, const int *spar,
+                const int *sleaf, const unsigned char *smask, const R *locL, double *sphi, R *sfld,
+                hipStream_t st);
+
 // far field at one level (declared here, defined with the matrix-core kernels)
 template <typename R>
 int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const R *phi, const R *zrow, R *loc,
@@ -841,10 +737,9 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
 
     // a7/a8: far field at the fragments and the near field
     pk = prof_begin(plan, st);
-    k_leaf<N, R><<<blocks(nfrag, 256), 256, 0, st>>>(g, t, den, nfrag, v.leafstart, v.su, v.sv, v.sw,
-                                                     v.sq, v.spar, v.sleaf, v.smask,
-                                                     v.loc + W.lvl[L] * O::NS, v.sphi, v.sfld);
-    EQ_CHECK(hipGetLastError());
+    rc = launch_near<N, R>(plan, nfrag, t, den, v.leafstart, v.su, v.sv, v.sw, v.sq, v.spar, v.sleaf, v.smask,
+                           v.loc + W.lvl[L] * O::NS, v.sphi, v.sfld, st);
+    if (rc) return rc;
     prof_end(plan, st, pk, EQFMM_STAGE_LEAF, 0.0, 0.0);
 
     // a9/a10: back to the charges, energy

@@ -464,11 +464,11 @@ int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, int cells
     return wgs;
 }
 
-// k-chunk per pipeline step: four float4 loads of A and of B per lane (a
-// larger chunk doubles the register stages and halves the resident waves)
+// k-chunk per pipeline step (float4 loads of A and of B per lane): 4 for
+// n <= 4, where more resident waves pay off, 8 above (measured)
 template <int N> struct MxChunk {
     static constexpr int NA = MxShape<N>::KH / 4;
-    static constexpr int CH = NA % 4 == 0 ? 4 : NA;
+    static constexpr int CH = N <= 4 ? (NA % 4 == 0 ? 4 : NA) : (NA % 8 == 0 ? 8 : (NA % 4 == 0 ? 4 : NA));
 };
 
 template <int N>

@@ -1,0 +1,409 @@
+// Far field at the charges (a7) and near field (a8): for every fragment,
+// Psi of its finest cell evaluated on the replacement of a unit charge there
+// (Sec. 2.2 step 4 and the force rule after step 5), plus the direct sum over
+// the same and the 26 adjacent finest cells (Sec. 1, Sec. 2.2 step 5);
+// fragments of the same charge do not interact.
+//
+// Work decomposition: fragments are sorted by finest cell in row-major order
+// (x fastest), so the cells x-1..x+1 of one row (y, z) are one contiguous
+// range.  A workgroup owns RB consecutive cells of one x-row (about 64
+// targets).  When its 9 neighbouring rows hold at most kChunk sources, it
+// stages them all in LDS at once and each target reads the sub-ranges of its
+// own three cells per row, with S = 2 or 4 threads per target taking every
+// S-th source (their sums are added in a fixed order at the end).  Dense
+// blocks (clustered charges) read the same windows from global memory
+// instead: the lanes of a wave then mostly share a cell and the loads are
+// broadcasts.  Targets whose charge is split are evaluated in
+// double even in the float modes (the force along a split axis is a short
+// sum of large cancelling terms).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace eqfmm {
+
+namespace {
+
+template <int N> struct NearShape {
+    static constexpr int N3 = N * N * N;
+    static constexpr int NS = (N3 + 15) & ~15;
+};
+
+constexpr int kChunk = 1024;   // staged sources of one row block
+constexpr int kDense = 256;    // row blocks with this many targets go to k_near_dense
+
+template <int N, typename C, typename R>
+__device__ __forceinline__ void l2p_part(const R *t_, const R *den_, const R *Lc, double ud, double vd,
+                                         double wd, C inv_s, int sl, int S, C &ph, C &f0, C &f1, C &f2)
+{
+    C t[N], den[N], gx[N], gy[N], gz[N], dx[N], dy[N], dz[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        t[k] = C(t_[k]);
+        den[k] = C(den_[k]);
+    }
+    const C u = C(ud), v = C(vd), w = C(wd);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        C p = C(1), dp = C(0), q = C(1), dq = C(0), r = C(1), dr = C(0);
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (k != i) {
+                dp = dp * (u - t[k]) + p;
+                p = p * (u - t[k]);
+                dq = dq * (v - t[k]) + q;
+                q = q * (v - t[k]);
+                dr = dr * (w - t[k]) + r;
+                r = r * (w - t[k]);
+            }
+        gx[i] = den[i] * p;
+        dx[i] = den[i] * dp;
+        gy[i] = den[i] * q;
+        dy[i] = den[i] * dq;
+        gz[i] = den[i] * r;
+        dz[i] = den[i] * dr;
+    }
+    C a0 = C(0), a1 = C(0), a2 = C(0), a3 = C(0);
+    for (int k = sl; k < N; k += S)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            C s0 = C(0), s1 = C(0);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const C l = C(Lc[i + N * j + N * N * k]);
+                s0 += gx[i] * l;
+                s1 += dx[i] * l;
+            }
+            a0 += gz[k] * gy[j] * s0;
+            a1 += gz[k] * gy[j] * s1;
+            a2 += gz[k] * dy[j] * s0;
+            a3 += dz[k] * gy[j] * s0;
+        }
+    ph += a0;
+    f0 -= a1 * inv_s;
+    f1 -= a2 * inv_s;
+    f2 -= a3 * inv_s;
+}
+
+template <typename R> __device__ __forceinline__ R rsqrt_t(R x);
+template <> __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+template <> __device__ __forceinline__ float rsqrt_t<float>(float x) { return rsqrtf(x); }
+
+// sources [jl, jh) of the staged chunk; displacement formed in double from
+// the cell-local coordinates and the cell offset (ex = target - source)
+template <typename C, typename R>
+__device__ __forceinline__ void p2p_range(const double *lu, const double *lv, const double *lw, const R *lq,
+                                          const int *lpar, const int *ldx, int jl, int jh, int S, double ud,
+                                          double vy, double wz, int tx, int par, double sd, C &ph, C &f0,
+                                          C &f1, C &f2)
+{
+    for (int j = jl; j < jh; j += S) {
+        if (lpar[j] == par) continue;
+        const C ex = C((ud + double(tx - ldx[j]) - lu[j]) * sd);
+        const C ey = C((vy - lv[j]) * sd);
+        const C ez = C((wz - lw[j]) * sd);
+        const C r2 = ex * ex + ey * ey + ez * ez;
+        const C ri = rsqrt_t<C>(r2);
+        const C qr = C(lq[j]) * ri;
+        const C qr3 = qr * ri * ri;
+        ph += qr;
+        f0 += qr3 * ex;
+        f1 += qr3 * ey;
+        f2 += qr3 * ez;
+    }
+}
+
+// One segment of source cells in a neighbouring row: cells [lo, hi) of row
+// base rb, whose unwrapped x index is the cell index + shift.
+struct Seg {
+    int rb, lo, hi, shift, dy, dz;
+};
+
+// the up to 27 segments (9 rows x main / left wrap / right wrap) of the
+// row block [c0, c1) of row (y, z); returns their number
+__device__ __forceinline__ int row_segments(const Geom &g, int y, int z, int c0, int c1, Seg *out)
+{
+    const int D = g.D;
+    int m = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+            int yy = y + dy, zz = z + dz;
+            if (g.periodic) {
+                yy = (yy + D) % D;
+                zz = (zz + D) % D;
+            } else if (yy < 0 || zz < 0 || yy >= D || zz >= D) {
+                continue;
+            }
+            const int rb = (yy + D * zz) * D;
+            out[m++] = Seg{rb, c0 - 1 > 0 ? c0 - 1 : 0, c1 + 1 < D ? c1 + 1 : D, 0, dy, dz};
+            if (g.periodic && c0 == 0) out[m++] = Seg{rb, D - 1, D, -D, dy, dz};
+            if (g.periodic && c1 == D) out[m++] = Seg{rb, 0, 1, D, dy, dz};
+        }
+    return m;
+}
+
+// sources of target cell tx inside segment sg: [j0, j1)
+__device__ __forceinline__ void window(const int *leafstart, const Seg &sg, int tx, int &j0, int &j1)
+{
+    int a = tx - 1 - sg.shift, b = tx + 1 - sg.shift;
+    a = a > sg.lo ? a : sg.lo;
+    b = b < sg.hi - 1 ? b : sg.hi - 1;
+    if (a > b) {
+        j0 = j1 = 0;
+        return;
+    }
+    j0 = leafstart[sg.rb + a];
+    j1 = leafstart[sg.rb + b + 1];
+}
+
+template <int N, typename R>
+__global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_, int RB, const int *leafstart,
+                                              const double *su, const double *sv, const double *sw, const R *sq,
+                                              const int *spar, const int *sleaf, const unsigned char *smask,
+                                              const R *locL, double *sphi, R *sfld)
+{
+    using O = NearShape<N>;
+    __shared__ double lu[kChunk], lv[kChunk], lw[kChunk];
+    __shared__ R lq[kChunk];
+    __shared__ int lpar[kChunk], ldx[kChunk];
+    __shared__ double red[3 * 4 * 64];   // slices 1..S-1, four sums, TT targets
+    __shared__ Seg segs[27];
+    __shared__ int sbase[28], nseg_s;
+    const int D = g.D;
+    const int nxb = (D + RB - 1) / RB;
+    const int row = blockIdx.x / nxb, xb = blockIdx.x - row * nxb;
+    const int y = row % D, z = row / D;
+    const int c0 = xb * RB, c1 = c0 + RB < D ? c0 + RB : D;
+    const int T0 = leafstart[row * D + c0], T1 = leafstart[row * D + c1];
+    const int T = T1 - T0;
+    // empty blocks, and dense blocks (k_near_dense), leave at once (uniform)
+    if (T == 0 || T >= kDense) return;
+    const double sd = g.s_leaf;
+    const bool mixed = sizeof(R) == sizeof(float) && g.continuous;
+    if (threadIdx.x == 0) {
+        const int m = row_segments(g, y, z, c0, c1, segs);
+        int base = 0;
+        for (int k = 0; k < m; ++k) {
+            sbase[k] = base;
+            base += leafstart[segs[k].rb + segs[k].hi] - leafstart[segs[k].rb + segs[k].lo];
+        }
+        sbase[m] = base;
+        nseg_s = m;
+    }
+    __syncthreads();
+    const int nseg = nseg_s, nsrc = sbase[nseg];
+    // Dense blocks read their windows from global memory (the lanes of a wave
+    // mostly share a cell, so the loads are broadcasts); sparse blocks stage
+    // every source once in LDS and split each target over S threads.
+    const bool staged = nsrc <= kChunk;
+    const int S = staged ? (T >= 128 ? 2 : 4) : 1;
+    const int TT = 256 / S;
+    const int tl = threadIdx.x % TT, sl = threadIdx.x / TT;
+    if (staged) {
+        for (int k = 0; k < nseg; ++k) {
+            const Seg sg = segs[k];
+            const int J0 = leafstart[sg.rb + sg.lo], len = sbase[k + 1] - sbase[k];
+            for (int i = threadIdx.x; i < len; i += 256) {
+                const int j = J0 + i, o = sbase[k] + i;
+                lu[o] = su[j];
+                lv[o] = sv[j];
+                lw[o] = sw[j];
+                lq[o] = sq[j];
+                lpar[o] = spar[j];
+                ldx[o] = sleaf[j] % D + sg.shift;
+            }
+        }
+        __syncthreads();
+    }
+    for (int tc = T0; tc < T1; tc += TT) {
+        const int t = tc + tl;
+        const bool act = t < T1;
+        const int tt = act ? t : T0;
+        const double ud = su[tt], vd = sv[tt], wd = sw[tt];
+        const int par = spar[tt];
+        const int tx = sleaf[tt] % D;
+        const bool dbl = mixed && smask[par];
+        R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
+        double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
+        const R *Lc = locL + int64_t(sleaf[tt]) * O::NS;
+        if (act) {
+            if (dbl) l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, sl, S, dph, df0, df1, df2);
+            else l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), sl, S, ph, f0, f1, f2);
+            for (int k = 0; k < nseg; ++k) {
+                const Seg sg = segs[k];
+                int j0, j1;
+                window(leafstart, sg, tx, j0, j1);
+                if (j0 >= j1) continue;
+                const double vy = vd - sg.dy, wz = wd - sg.dz;
+                if (staged) {
+                    const int off = sbase[k] - leafstart[sg.rb + sg.lo];
+                    if (dbl)
+                        p2p_range<double, R>(lu, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, ud, vy, wz, tx,
+                                             par, sd, dph, df0, df1, df2);
+                    else
+                        p2p_range<R, R>(lu, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, ud, vy, wz, tx, par,
+                                        sd, ph, f0, f1, f2);
+                } else {
+                    // global reads; the unwrapped cell offset is the segment's
+                    const int sx0 = tx;
+                    for (int j = j0; j < j1; ++j) {
+                        if (spar[j] == par) continue;
+                        const int dxc = sleaf[j] % D + sg.shift;
+                        if (dbl) {
+                            const double ex = (ud + double(sx0 - dxc) - su[j]) * sd;
+                            const double ey = (vy - sv[j]) * sd, ez = (wz - sw[j]) * sd;
+                            const double r2 = ex * ex + ey * ey + ez * ez;
+                            const double ri = 1.0 / sqrt(r2);
+                            const double qr = double(sq[j]) * ri, qr3 = qr * ri * ri;
+                            dph += qr;
+                            df0 += qr3 * ex;
+                            df1 += qr3 * ey;
+                            df2 += qr3 * ez;
+                        } else {
+                            const R ex = R((ud + double(sx0 - dxc) - su[j]) * sd);
+                            const R ey = R((vy - sv[j]) * sd), ez = R((wz - sw[j]) * sd);
+                            const R r2 = ex * ex + ey * ey + ez * ez;
+                            const R ri = rsqrt_t<R>(r2);
+                            const R qr = sq[j] * ri, qr3 = qr * ri * ri;
+                            ph += qr;
+                            f0 += qr3 * ex;
+                            f1 += qr3 * ey;
+                            f2 += qr3 * ez;
+                        }
+                    }
+                }
+            }
+        }
+        // add the slices of each target in a fixed order
+        double o0 = dbl ? dph : double(ph), o1 = dbl ? df0 : double(f0);
+        double o2 = dbl ? df1 : double(f1), o3 = dbl ? df2 : double(f2);
+        if (S > 1) {
+            __syncthreads();
+            if (sl > 0) {
+                double *r = red + (sl - 1) * 4 * TT + tl;
+                r[0] = o0;
+                r[TT] = o1;
+                r[2 * TT] = o2;
+                r[3 * TT] = o3;
+            }
+            __syncthreads();
+            if (sl == 0)
+                for (int h = 0; h < S - 1; ++h) {
+                    const double *r = red + h * 4 * TT + tl;
+                    o0 += r[0];
+                    o1 += r[TT];
+                    o2 += r[2 * TT];
+                    o3 += r[3 * TT];
+                }
+        }
+        if (act && sl == 0) {
+            sphi[t] = o0;
+            sfld[3 * int64_t(t) + 0] = R(o1);
+            sfld[3 * int64_t(t) + 1] = R(o2);
+            sfld[3 * int64_t(t) + 2] = R(o3);
+        }
+    }
+}
+
+
+// Targets of dense row blocks (>= kDense targets), one thread each over the
+// sorted fragments: the lanes of a wave then mostly share a cell, so every
+// source load is a broadcast, and a large cluster spreads over many waves.
+template <int N, typename R>
+__global__ void __launch_bounds__(256) k_near_dense(Geom g, const R *t_, const R *den_, int RB, int64_t nfrag,
+                                                    const int *leafstart, const double *su, const double *sv,
+                                                    const double *sw, const R *sq, const int *spar,
+                                                    const int *sleaf, const unsigned char *smask, const R *locL,
+                                                    double *sphi, R *sfld)
+{
+    using O = NearShape<N>;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nfrag) return;
+    const int D = g.D;
+    const int leaf = sleaf[t];
+    const int tx = leaf % D, row = leaf / D, y = row % D, z = row / D;
+    const int c0 = (tx / RB) * RB, c1 = c0 + RB < D ? c0 + RB : D;
+    if (leafstart[row * D + c1] - leafstart[row * D + c0] < kDense) return;
+    const double sd = g.s_leaf;
+    const double ud = su[t], vd = sv[t], wd = sw[t];
+    const int par = spar[t];
+    const bool dbl = sizeof(R) == sizeof(float) && g.continuous && smask[par];
+    const R *Lc = locL + int64_t(leaf) * O::NS;
+    R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
+    double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
+    if (dbl) l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, 0, 1, dph, df0, df1, df2);
+    else l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), 0, 1, ph, f0, f1, f2);
+    Seg segs[27];
+    const int nseg = row_segments(g, y, z, tx, tx + 1, segs);
+    for (int k = 0; k < nseg; ++k) {
+        const Seg sg = segs[k];
+        int j0, j1;
+        window(leafstart, sg, tx, j0, j1);
+        const double vy = vd - sg.dy, wz = wd - sg.dz;
+        for (int j = j0; j < j1; ++j) {
+            if (spar[j] == par) continue;
+            const int dxc = sleaf[j] % D + sg.shift;
+            if (dbl) {
+                const double ex = (ud + double(tx - dxc) - su[j]) * sd;
+                const double ey = (vy - sv[j]) * sd, ez = (wz - sw[j]) * sd;
+                const double r2 = ex * ex + ey * ey + ez * ez;
+                const double ri = 1.0 / sqrt(r2);
+                const double qr = double(sq[j]) * ri, qr3 = qr * ri * ri;
+                dph += qr;
+                df0 += qr3 * ex;
+                df1 += qr3 * ey;
+                df2 += qr3 * ez;
+            } else {
+                const R ex = R((ud + double(tx - dxc) - su[j]) * sd);
+                const R ey = R((vy - sv[j]) * sd), ez = R((wz - sw[j]) * sd);
+                const R r2 = ex * ex + ey * ey + ez * ez;
+                const R ri = rsqrt_t<R>(r2);
+                const R qr = sq[j] * ri, qr3 = qr * ri * ri;
+                ph += qr;
+                f0 += qr3 * ex;
+                f1 += qr3 * ey;
+                f2 += qr3 * ez;
+            }
+        }
+    }
+    sphi[t] = dbl ? dph : double(ph);
+    sfld[3 * t + 0] = R(dbl ? df0 : double(f0));
+    sfld[3 * t + 1] = R(dbl ? df1 : double(f1));
+    sfld[3 * t + 2] = R(dbl ? df2 : double(f2));
+}
+
+}  // namespace
+
+// cells per workgroup row block: about 64 targets on average
+template <int N, typename R>
+int launch_near(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const int *leafstart,
+                const double *su, const double *sv, const double *sw, const R *sq, const int *spar,
+                const int *sleaf, const unsigned char *smask, const R *locL, double *sphi, R *sfld,
+                hipStream_t st)
+{
+    const Geom &g = plan->g;
+    const double mean = double(nfrag) / (double(g.D) * g.D * g.D);
+    int RB = int(64.0 / (mean > 1e-9 ? mean : 1e-9) + 0.5);
+    RB = RB < 1 ? 1 : (RB > g.D ? g.D : RB);
+    const int nxb = (g.D + RB - 1) / RB;
+    const int64_t grid = int64_t(g.D) * g.D * nxb;
+    k_near<N, R><<<dim3(unsigned(grid)), 256, 0, st>>>(g, t, den, RB, leafstart, su, sv, sw, sq, spar, sleaf,
+                                                       smask, locL, sphi, sfld);
+    if (nfrag > 0)
+        k_near_dense<N, R><<<dim3(unsigned((nfrag + 255) / 256)), 256, 0, st>>>(
+            g, t, den, RB, nfrag, leafstart, su, sv, sw, sq, spar, sleaf, smask, locL, sphi, sfld);
+    return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+}
+
+#define EQ_NEAR_INST(NN, RR)                                                                              \
+    template int launch_near<NN, RR>(const eqfmm_plan *, int64_t, const RR *, const RR *, const int *,    \
+                                     const double *, const double *, const double *, const RR *,        \
+                                     const int *, const int *, const unsigned char *, const RR *,       \
+                                     double *, RR *, hipStream_t);
+EQ_NEAR_INST(2, float) EQ_NEAR_INST(3, float) EQ_NEAR_INST(4, float) EQ_NEAR_INST(5, float)
+EQ_NEAR_INST(6, float) EQ_NEAR_INST(7, float)
+EQ_NEAR_INST(2, double) EQ_NEAR_INST(3, double) EQ_NEAR_INST(4, double) EQ_NEAR_INST(5, double)
+EQ_NEAR_INST(6, double) EQ_NEAR_INST(7, double)
+#undef EQ_NEAR_INST
+
+}  // namespace eqfmm
