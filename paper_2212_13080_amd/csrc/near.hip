@@ -31,6 +31,7 @@ template <int N> struct NearShape {
 
 constexpr int kChunk = 1024;   // staged sources of one row block
 constexpr int kDense = 256;    // row blocks with this many targets go to k_near_dense
+constexpr int kMaxRB = 64;     // cells per row block at most
 
 template <int N, typename C, typename R>
 __device__ __forceinline__ void l2p_part(const R *t_, const R *den_, const R *Lc, double ud, double vd,
@@ -87,7 +88,24 @@ __device__ __forceinline__ void l2p_part(const R *t_, const R *den_, const R *Lc
 
 template <typename R> __device__ __forceinline__ R rsqrt_t(R x);
 template <> __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
-template <> __device__ __forceinline__ float rsqrt_t<float>(float x) { return rsqrtf(x); }
+// the hardware reciprocal square root (1 ulp); r^2 of two distinct charges
+// is never a float denormal at the box scales in use
+template <> __device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Coulomb term of one source at displacement (ex, ey, ez) = target - source;
+// a fragment of the target's own charge (self included) adds exact zeros
+template <typename C>
+__device__ __forceinline__ void p2p_term(C ex, C ey, C ez, C q, bool self, C &ph, C &f0, C &f1, C &f2)
+{
+    const C r2 = self ? C(1) : ex * ex + ey * ey + ez * ez;
+    const C ri = rsqrt_t<C>(r2);
+    const C qr = (self ? C(0) : q) * ri;
+    const C qr3 = qr * ri * ri;
+    ph += qr;
+    f0 += qr3 * ex;
+    f1 += qr3 * ey;
+    f2 += qr3 * ez;
+}
 
 // sources [jl, jh) of the staged chunk; displacement formed in double from
 // the cell-local coordinates and the cell offset (ex = target - source)
@@ -97,19 +115,12 @@ __device__ __forceinline__ void p2p_range(const double *lu, const double *lv, co
                                           double vy, double wz, int tx, int par, double sd, C &ph, C &f0,
                                           C &f1, C &f2)
 {
+#pragma unroll 2
     for (int j = jl; j < jh; j += S) {
-        if (lpar[j] == par) continue;
         const C ex = C((ud + double(tx - ldx[j]) - lu[j]) * sd);
         const C ey = C((vy - lv[j]) * sd);
         const C ez = C((wz - lw[j]) * sd);
-        const C r2 = ex * ex + ey * ey + ez * ez;
-        const C ri = rsqrt_t<C>(r2);
-        const C qr = C(lq[j]) * ri;
-        const C qr3 = qr * ri * ri;
-        ph += qr;
-        f0 += qr3 * ex;
-        f1 += qr3 * ey;
-        f2 += qr3 * ez;
+        p2p_term<C>(ex, ey, ez, C(lq[j]), lpar[j] == par, ph, f0, f1, f2);
     }
 }
 
@@ -167,8 +178,12 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
     __shared__ R lq[kChunk];
     __shared__ int lpar[kChunk], ldx[kChunk];
     __shared__ double red[3 * 4 * 64];   // slices 1..S-1, four sums, TT targets
+    // segment 3r + kind of neighbour row r = 3 (dz + 1) + (dy + 1): kind 0 is
+    // the cells c0-1 .. c1 of that row, kinds 1 and 2 the periodic images of
+    // cells D-1 and 0 beyond the walls; unused segments are empty (lo == hi)
     __shared__ Seg segs[27];
-    __shared__ int sbase[28], nseg_s;
+    __shared__ int sbase[28], sj0[27];
+    __shared__ int rls[9][kMaxRB + 3];   // leafstart of cells c0-1 .. c1+1 (clamped to [0, D]) of each row
     const int D = g.D;
     const int nxb = (D + RB - 1) / RB;
     const int row = blockIdx.x / nxb, xb = blockIdx.x - row * nxb;
@@ -180,38 +195,90 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
     if (T == 0 || T >= kDense) return;
     const double sd = g.s_leaf;
     const bool mixed = sizeof(R) == sizeof(float) && g.continuous;
-    if (threadIdx.x == 0) {
-        const int m = row_segments(g, y, z, c0, c1, segs);
-        int base = 0;
-        for (int k = 0; k < m; ++k) {
-            sbase[k] = base;
-            base += leafstart[segs[k].rb + segs[k].hi] - leafstart[segs[k].rb + segs[k].lo];
+    auto row_base = [&](int r, bool &ok) {
+        int yy = y + r % 3 - 1, zz = z + r / 3 - 1;
+        if (g.periodic) {
+            yy = (yy + D) % D;
+            zz = (zz + D) % D;
+            ok = true;
+        } else {
+            ok = yy >= 0 && zz >= 0 && yy < D && zz < D;
         }
-        sbase[m] = base;
-        nseg_s = m;
+        return (yy + D * zz) * D;
+    };
+    const int W = c1 - c0 + 3;
+    for (int idx = threadIdx.x; idx < 9 * W; idx += 256) {
+        const int r = idx / W, i = idx - r * W;
+        bool ok;
+        const int rb = row_base(r, ok);
+        int c = c0 - 1 + i;
+        c = c < 0 ? 0 : (c > D ? D : c);
+        rls[r][i] = ok ? leafstart[rb + c] : 0;
+    }
+    if (threadIdx.x < 64) {   // wave 0: segments and their exclusive prefix
+        const int k = threadIdx.x;
+        int cnt = 0;
+        if (k < 27) {
+            const int r = k / 3, kind = k - 3 * r;
+            bool ok;
+            const int rb = row_base(r, ok);
+            Seg sg{rb, 0, 0, 0, r % 3 - 1, r / 3 - 1};
+            if (ok) {
+                if (kind == 0) {
+                    sg.lo = c0 - 1 > 0 ? c0 - 1 : 0;
+                    sg.hi = c1 + 1 < D ? c1 + 1 : D;
+                } else if (kind == 1 && g.periodic && c0 == 0) {
+                    sg.lo = D - 1;
+                    sg.hi = D;
+                    sg.shift = -D;
+                } else if (kind == 2 && g.periodic && c1 == D) {
+                    sg.lo = 0;
+                    sg.hi = 1;
+                    sg.shift = D;
+                }
+            }
+            int j0 = 0;
+            if (sg.hi > sg.lo) {
+                j0 = leafstart[rb + sg.lo];
+                cnt = leafstart[rb + sg.hi] - j0;
+            }
+            segs[k] = sg;
+            sj0[k] = j0;
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (k >= off) incl += v;
+        }
+        if (k < 27) sbase[k] = incl - cnt;
+        if (k == 26) sbase[27] = incl;
     }
     __syncthreads();
-    const int nseg = nseg_s, nsrc = sbase[nseg];
-    // Dense blocks read their windows from global memory (the lanes of a wave
-    // mostly share a cell, so the loads are broadcasts); sparse blocks stage
-    // every source once in LDS and split each target over S threads.
+    const int nsrc = sbase[27];
+    // Sparse blocks stage every source once in LDS and split each target over
+    // S threads; dense neighbourhoods are read from global memory.
     const bool staged = nsrc <= kChunk;
     const int S = staged ? (T >= 128 ? 2 : 4) : 1;
     const int TT = 256 / S;
     const int tl = threadIdx.x % TT, sl = threadIdx.x / TT;
     if (staged) {
-        for (int k = 0; k < nseg; ++k) {
-            const Seg sg = segs[k];
-            const int J0 = leafstart[sg.rb + sg.lo], len = sbase[k + 1] - sbase[k];
-            for (int i = threadIdx.x; i < len; i += 256) {
-                const int j = J0 + i, o = sbase[k] + i;
-                lu[o] = su[j];
-                lv[o] = sv[j];
-                lw[o] = sw[j];
-                lq[o] = sq[j];
-                lpar[o] = spar[j];
-                ldx[o] = sleaf[j] % D + sg.shift;
-            }
+#pragma unroll
+        for (int m = 0; m < kChunk / 256; ++m) {
+            const int o = threadIdx.x + 256 * m;
+            if (o >= nsrc) break;
+            // the last segment that starts at or before o (it holds o)
+            int k = 0;
+#pragma unroll
+            for (int step = 16; step > 0; step >>= 1)
+                if (k + step < 27 && sbase[k + step] <= o) k += step;
+            const int j = sj0[k] + (o - sbase[k]);
+            lu[o] = su[j];
+            lv[o] = sv[j];
+            lw[o] = sw[j];
+            lq[o] = sq[j];
+            lpar[o] = spar[j];
+            ldx[o] = (sleaf[j] & (D - 1)) + segs[k].shift;
         }
         __syncthreads();
     }
@@ -221,22 +288,35 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
         const int tt = act ? t : T0;
         const double ud = su[tt], vd = sv[tt], wd = sw[tt];
         const int par = spar[tt];
-        const int tx = sleaf[tt] % D;
+        const int leaf = sleaf[tt];
+        const int tx = leaf & (D - 1);
         const bool dbl = mixed && smask[par];
         R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
         double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
-        const R *Lc = locL + int64_t(sleaf[tt]) * O::NS;
+        const R *Lc = locL + int64_t(leaf) * O::NS;
         if (act) {
             if (dbl) l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, sl, S, dph, df0, df1, df2);
             else l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), sl, S, ph, f0, f1, f2);
-            for (int k = 0; k < nseg; ++k) {
+            for (int k = 0; k < 27; ++k) {
                 const Seg sg = segs[k];
+                if (sg.hi == sg.lo) continue;
+                // sources of cells tx-1 .. tx+1 in this segment, as global indices
                 int j0, j1;
-                window(leafstart, sg, tx, j0, j1);
-                if (j0 >= j1) continue;
+                if (sg.shift == 0) {
+                    const int a = tx - 1 > sg.lo ? tx - 1 : sg.lo;
+                    const int b = tx + 1 < sg.hi - 1 ? tx + 1 : sg.hi - 1;
+                    if (a > b) continue;
+                    j0 = rls[k / 3][a - (c0 - 1)];
+                    j1 = rls[k / 3][b + 1 - (c0 - 1)];
+                } else {
+                    // an image cell beyond a wall neighbours only the cell at that wall
+                    if (sg.shift < 0 ? tx != 0 : tx != D - 1) continue;
+                    j0 = sj0[k];
+                    j1 = j0 + (sbase[k + 1] - sbase[k]);
+                }
                 const double vy = vd - sg.dy, wz = wd - sg.dz;
                 if (staged) {
-                    const int off = sbase[k] - leafstart[sg.rb + sg.lo];
+                    const int off = sbase[k] - sj0[k];
                     if (dbl)
                         p2p_range<double, R>(lu, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, ud, vy, wz, tx,
                                              par, sd, dph, df0, df1, df2);
@@ -244,32 +324,12 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
                         p2p_range<R, R>(lu, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, ud, vy, wz, tx, par,
                                         sd, ph, f0, f1, f2);
                 } else {
-                    // global reads; the unwrapped cell offset is the segment's
-                    const int sx0 = tx;
                     for (int j = j0; j < j1; ++j) {
-                        if (spar[j] == par) continue;
-                        const int dxc = sleaf[j] % D + sg.shift;
-                        if (dbl) {
-                            const double ex = (ud + double(sx0 - dxc) - su[j]) * sd;
-                            const double ey = (vy - sv[j]) * sd, ez = (wz - sw[j]) * sd;
-                            const double r2 = ex * ex + ey * ey + ez * ez;
-                            const double ri = 1.0 / sqrt(r2);
-                            const double qr = double(sq[j]) * ri, qr3 = qr * ri * ri;
-                            dph += qr;
-                            df0 += qr3 * ex;
-                            df1 += qr3 * ey;
-                            df2 += qr3 * ez;
-                        } else {
-                            const R ex = R((ud + double(sx0 - dxc) - su[j]) * sd);
-                            const R ey = R((vy - sv[j]) * sd), ez = R((wz - sw[j]) * sd);
-                            const R r2 = ex * ex + ey * ey + ez * ez;
-                            const R ri = rsqrt_t<R>(r2);
-                            const R qr = sq[j] * ri, qr3 = qr * ri * ri;
-                            ph += qr;
-                            f0 += qr3 * ex;
-                            f1 += qr3 * ey;
-                            f2 += qr3 * ez;
-                        }
+                        const double ex = ud + double(tx - ((sleaf[j] & (D - 1)) + sg.shift)) - su[j];
+                        const double ey = vy - sv[j], ez = wz - sw[j];
+                        const bool self = spar[j] == par;
+                        if (dbl) p2p_term<double>(ex * sd, ey * sd, ez * sd, double(sq[j]), self, dph, df0, df1, df2);
+                        else p2p_term<R>(R(ex * sd), R(ey * sd), R(ez * sd), sq[j], self, ph, f0, f1, f2);
                     }
                 }
             }
@@ -341,29 +401,11 @@ __global__ void __launch_bounds__(256) k_near_dense(Geom g, const R *t_, const R
         window(leafstart, sg, tx, j0, j1);
         const double vy = vd - sg.dy, wz = wd - sg.dz;
         for (int j = j0; j < j1; ++j) {
-            if (spar[j] == par) continue;
-            const int dxc = sleaf[j] % D + sg.shift;
-            if (dbl) {
-                const double ex = (ud + double(tx - dxc) - su[j]) * sd;
-                const double ey = (vy - sv[j]) * sd, ez = (wz - sw[j]) * sd;
-                const double r2 = ex * ex + ey * ey + ez * ez;
-                const double ri = 1.0 / sqrt(r2);
-                const double qr = double(sq[j]) * ri, qr3 = qr * ri * ri;
-                dph += qr;
-                df0 += qr3 * ex;
-                df1 += qr3 * ey;
-                df2 += qr3 * ez;
-            } else {
-                const R ex = R((ud + double(tx - dxc) - su[j]) * sd);
-                const R ey = R((vy - sv[j]) * sd), ez = R((wz - sw[j]) * sd);
-                const R r2 = ex * ex + ey * ey + ez * ez;
-                const R ri = rsqrt_t<R>(r2);
-                const R qr = sq[j] * ri, qr3 = qr * ri * ri;
-                ph += qr;
-                f0 += qr3 * ex;
-                f1 += qr3 * ey;
-                f2 += qr3 * ez;
-            }
+            const double ex = ud + double(tx - ((sleaf[j] & (D - 1)) + sg.shift)) - su[j];
+            const double ey = vy - sv[j], ez = wz - sw[j];
+            const bool self = spar[j] == par;
+            if (dbl) p2p_term<double>(ex * sd, ey * sd, ez * sd, double(sq[j]), self, dph, df0, df1, df2);
+            else p2p_term<R>(R(ex * sd), R(ey * sd), R(ez * sd), sq[j], self, ph, f0, f1, f2);
         }
     }
     sphi[t] = dbl ? dph : double(ph);
@@ -385,6 +427,7 @@ int launch_near(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den,
     const double mean = double(nfrag) / (double(g.D) * g.D * g.D);
     int RB = int(64.0 / (mean > 1e-9 ? mean : 1e-9) + 0.5);
     RB = RB < 1 ? 1 : (RB > g.D ? g.D : RB);
+    RB = RB > kMaxRB ? kMaxRB : RB;
     const int nxb = (g.D + RB - 1) / RB;
     const int64_t grid = int64_t(g.D) * g.D * nxb;
     k_near<N, R><<<dim3(unsigned(grid)), 256, 0, st>>>(g, t, den, RB, leafstart, su, sv, sw, sq, spar, sleaf,
