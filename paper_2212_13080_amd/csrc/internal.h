@@ -15,6 +15,7 @@ constexpr int kMaxOrder = 7;
 constexpr int kMaxPieces = kMaxOrder + 1;   // split pieces along one axis (odd n: n + 1)
 constexpr int kNumOffsets = 343;            // 7^3 displacements between same-level cells
 constexpr int kListLen = 192;               // interaction list (189) padded for the far-field kernels
+constexpr int kHalo = 3;                    // halo cells around each level of the far-field input
 
 // Geometry shared by every kernel (passed by value).
 struct Geom {
@@ -36,7 +37,10 @@ struct DevOps {
     const void *K;          // Coulomb matrices [343][n3][n3] at unit cell side
     const void *T;          // periodic root operator [n3][n3] at unit box side
     const void *Kmx;        // matrix-core operand layout of K (precision specific)
-    const void *offs;       // interaction lists per parity: int8 [8][kListLen][3]
+    const int *mxtab;       // interaction lists [level][parity][kListLen], packed
+                            // (delta << 9) | oi: delta = source row - target row in
+                            // the haloed layout of that level, oi = 0..342 the
+                            // displacement's matrix
 };
 
 // Host plan (the public opaque type).
@@ -61,10 +65,11 @@ struct WsLayout {
     size_t hdr, cnt, fstart, smask, leafcnt, leafstart, cursor, scanblk;
     size_t su, sv, sw, sq, spar, sleaf;
     size_t gslot, gw, gdw;
-    size_t phi, loc, sphi, sfld, epart;
+    size_t phi, phipad, loc, sphi, sfld, epart;
     size_t total;
     int64_t scan_blocks, e_blocks;
     std::vector<int64_t> lvl;     // first cell of each level in the Phi / L arrays
+    std::vector<int64_t> plvl;    // first cell of each interaction level in the haloed Phi
 };
 
 struct WsHeader {
@@ -82,7 +87,7 @@ struct eqfmm_plan {
     eqfmm::Geom g;
     eqfmm::HostOps h;
     std::vector<unsigned char> image;     // device image, built at create
-    size_t off_t, off_den, off_t64, off_seg, off_segden, off_G, off_K, off_T, off_Kmx, off_offs;
+    size_t off_t, off_den, off_t64, off_seg, off_segden, off_G, off_K, off_T, off_Kmx, off_mxtab;
     void *dev = nullptr;
     eqfmm::DevOps ops{};
     // forward state consumed by backward

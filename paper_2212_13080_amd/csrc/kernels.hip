@@ -599,7 +599,7 @@ template <typename R> struct Ws {
     WsHeader *hdr;
     int *cnt, *fstart, *leafcnt, *leafstart, *cursor, *scanblk, *spar, *sleaf, *gslot;
     unsigned char *smask;
-    R *sq, *phi, *loc, *sfld;
+    R *sq, *phi, *phipad, *loc, *sfld;
     double *su, *sv, *sw, *gw, *gdw, *sphi, *epart;
 };
 
@@ -624,6 +624,7 @@ template <typename R> Ws<R> views(unsigned char *b, const WsLayout &W)
     v.gw = reinterpret_cast<double *>(b + W.gw);
     v.gdw = reinterpret_cast<double *>(b + W.gdw);
     v.phi = reinterpret_cast<R *>(b + W.phi);
+    v.phipad = reinterpret_cast<R *>(b + W.phipad);
     v.loc = reinterpret_cast<R *>(b + W.loc);
     v.sphi = reinterpret_cast<double *>(b + W.sphi);
     v.sfld = reinterpret_cast<R *>(b + W.sfld);
@@ -642,10 +643,15 @@ int launch_near(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den,
                 const int *sleaf, const unsigned char *smask, const R *locL, double *sphi, R *sfld,
                 hipStream_t st);
 
-// far field at one level (declared here, defined with the matrix-core kernels)
+// far field (declared here, defined with the matrix-core kernels in m2l.hip):
+// the haloed copy of Phi at levels lmin..lmax, then the products of every
+// interaction level
 template <typename R>
-int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const R *phi, const R *zrow, R *loc,
-               hipStream_t st);
+int launch_m2l_pad(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const R *phi,
+                   R *phipad, hipStream_t st);
+template <typename R>
+int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const R *phipad,
+               R *loc, hipStream_t st);
 
 template <int N, typename R>
 int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi_out,
@@ -665,9 +671,6 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     EQ_CHECK(hipMemsetAsync(v.hdr, 0, sizeof(WsHeader), st));
     EQ_CHECK(hipMemsetAsync(v.leafcnt, 0, 4 * (nleaf + 1), st));
     EQ_CHECK(hipMemsetAsync(v.cursor, 0, 4 * nleaf, st));
-    // a row of zeros after the last level: the far-field kernels read it for
-    // sources outside the box
-    EQ_CHECK(hipMemsetAsync(v.phi + W.lvl[g.L + 1] * O::NS, 0, O::NS * rs, st));
     k_count<N><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, n, pos, q, v.cnt, v.smask, v.leafcnt, v.hdr);
     EQ_CHECK(hipGetLastError());
     int rc = scan(v.cnt, v.fstart, n, v.scanblk, st);
@@ -713,6 +716,9 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
                                                            v.phi + W.lvl[l - 1] * O::NS);
         EQ_CHECK(hipGetLastError());
     }
+    // every interaction level again with its halo (the far-field input)
+    rc = launch_m2l_pad<R>(plan, lmin, L, W.lvl.data(), W.plvl.data(), v.phi, v.phipad, st);
+    if (rc) return rc;
     prof_end(plan, st, pk, EQFMM_STAGE_M2M, 0.0, 0.0);
 
     // a5/a6: downward pass.  The far-field products of every interaction
@@ -723,7 +729,7 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
         k_root<R><<<1, 256, 0, st>>>(static_cast<const R *>(ops.T), O::N3, R(1.0 / g.box), v.phi, v.loc);
         EQ_CHECK(hipGetLastError());
     }
-    rc = launch_m2l<R>(plan, lmin, L, W.lvl.data(), v.phi, v.phi + W.lvl[L + 1] * O::NS, v.loc, st);
+    rc = launch_m2l<R>(plan, lmin, L, W.lvl.data(), W.plvl.data(), v.phipad, v.loc, st);
     if (rc) return rc;
     // free space: Psi vanishes at levels 0 and 1, so the shifts start at 2 -> 3
     for (int l = g.periodic ? 1 : 3; l <= L; ++l) {

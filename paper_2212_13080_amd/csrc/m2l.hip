@@ -35,7 +35,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 struct MxLevels {
     int nlev;
     int level[8], ntile[8], wg_begin[9];
-    int64_t cell0[8];      // first cell of the level in the Phi / L arrays
+    int64_t cell0[8];      // first cell of the level in the L array
+    int64_t pcell0[8];     // first cell of the level in the haloed Phi
     float inv_side[8];
     double inv_side64[8];
 };
@@ -57,6 +58,9 @@ __device__ __forceinline__ int compact3(int64_t m)
 }
 
 int nb_of(int n3) { return (n3 + 31) / 32; }
+
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 
 // compile-time loop: f(integral_constant<int, I>) for I in [B, E)
 template <int B, int E, typename F>
@@ -129,6 +133,43 @@ void mx_layout_fill(const Geom &g, int precision, const std::vector<double> &K, 
     }
 }
 
+// ------------------------------------------------------------- halo copy
+
+// Levels of one halo-copy launch: rows [row0[i], row0[i+1]) belong to level
+// level[i], read from cell src0[i] of Phi and written from cell dst0[i] of
+// the haloed copy.
+struct MxPad {
+    int nlev;
+    int level[10];
+    int64_t row0[11];
+    int64_t src0[10], dst0[10];
+};
+
+// Phi of the interaction levels in the haloed layout: level l becomes a cube
+// of side P = 2^l + 2 kHalo whose cell (x, y, z), counted from -kHalo, holds
+// Phi_{x,y,z} inside the box, the periodic image in the periodic modes and
+// zero in free space outside it.  One thread per 16 bytes of a row.
+template <typename V, int VPR>
+__global__ void __launch_bounds__(256) k_m2l_pad(MxPad pd, int periodic, const V *__restrict__ phi,
+                                                 V *__restrict__ pad)
+{
+    const int64_t gid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t row = gid / VPR;
+    const int e = int(gid - row * VPR);
+    if (row >= pd.row0[pd.nlev]) return;
+    int li = 0;
+    while (li + 1 < pd.nlev && row >= pd.row0[li + 1]) ++li;
+    const int r = int(row - pd.row0[li]);
+    const int D = 1 << pd.level[li], P = D + 2 * kHalo;
+    const int x = r % P - kHalo, y = (r / P) % P - kHalo, z = r / (P * P) - kHalo;
+    V v = {};
+    if (periodic || (x >= 0 && y >= 0 && z >= 0 && x < D && y < D && z < D)) {
+        const int64_t c = (x & (D - 1)) + int64_t(D) * ((y & (D - 1)) + int64_t(D) * (z & (D - 1)));
+        v = phi[(pd.src0[li] + c) * VPR + e];
+    }
+    pad[(pd.dst0[li] + r) * VPR + e] = v;
+}
+
 // --------------------------------------------------------------- kernels
 
 // grid: round_up(8 * NB * ceil(ntile / 4), 8) workgroups of 4 waves; the
@@ -136,16 +177,19 @@ void mx_layout_fill(const Geom &g, int precision, const std::vector<double> &K, 
 // range of (parity, node block, tile) work, i.e. mostly one parity and
 // hence one set of 189 matrices in its L2.
 //
+// Sources are read from the haloed copy of Phi, where the source of every
+// target of a tile lies at the same row distance for a given displacement:
+// the address of a step is a wave-uniform base (scalar registers) plus a
+// per-lane offset fixed for the whole list, and no bounds tests are needed.
+//
 // The walk over (displacement, k-chunk) steps is software pipelined: the
 // operands of step s+1 are loaded into the second register stage while the
 // matrix cores work on step s.  Each displacement's product goes to a fresh
 // accumulator pair that is added to float running sums when the
 // displacement is complete.
-template <int N, bool BF16, int CH, bool PERIODIC, int NSPLIT>
-__global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__ Kmx,
-                                                const signed char *__restrict__ offs, MxLevels lv,
-                                                const float *__restrict__ phi_all,
-                                                const float *__restrict__ zrow,
+template <int N, bool BF16, int CH, int NSPLIT, int NST>
+__global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, const int *__restrict__ mxtab,
+                                                MxLevels lv, const float *__restrict__ phipad,
                                                 float *__restrict__ loc_all, int nwg)
 {
     using S = MxShape<N>;
@@ -154,6 +198,9 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     constexpr int NCH = NA / CH;          // pipeline steps per displacement
     static_assert(NA % CH == 0, "chunking");
     static_assert(!BF16 || CH % 2 == 0, "bf16 steps take 8 sources per lane");
+    using BT = typename std::conditional<BF16, bf16x8, float4>::type;
+    constexpr int NBL = BF16 ? CH / 2 : CH;   // B loads per step
+    constexpr int NBK = BF16 ? NA / 2 : NA;   // B vectors per lane, node block and displacement
     const int per = gridDim.x >> 3;
     int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (wg >= nwg) return;
@@ -162,7 +209,6 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     wg -= lv.wg_begin[li];
     const int level = lv.level[li], ntile = lv.ntile[li];
     const float inv_side = lv.inv_side[li];
-    const float *phi = phi_all + lv.cell0[li] * NS;
     float *loc = loc_all + lv.cell0[li] * NS;
     // a workgroup of 4 waves holds TPW = 4 / NSPLIT tiles; NSPLIT waves share
     // one tile, each running a contiguous part of the interaction list, and
@@ -172,75 +218,74 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
     const int tg = wg % ntg, pn = wg / ntg;
     const int nb = pn % NB, p = pn / NB;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    // wave index as a uniform value: the tile, list range and addresses
+    // derived from it then live in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tg * TPW + wv % TPW;
     const int hs = wv / TPW;
     constexpr int OPS = kListLen / NSPLIT;           // even: displacements go in pairs
     static_assert(kListLen % (2 * NSPLIT) == 0, "list padding");
     const int o_begin = hs * OPS, o_end = o_begin + OPS;
-    // the interaction list of this parity, packed (ox+3) | (oy+3) << 4 | (oz+3) << 8
-    __shared__ int soff[kListLen];
-    if (threadIdx.x < kListLen) {
-        const signed char *q = offs + (p * kListLen + threadIdx.x) * 3;
-        soff[threadIdx.x] = (q[0] + 3) | ((q[1] + 3) << 4) | ((q[2] + 3) << 8);
-    }
-    __syncthreads();
     const bool active = t < ntile;
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
-    const int D = 1 << level, Dp = D >> 1;
+    const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
     const int i = lane & 31, gh = lane >> 5;
-    const int64_t Pm = int64_t(t) * 32 + i;
-    const bool cvalid = Pm < nparent;
-    const int cx = 2 * compact3(Pm) + px, cy = 2 * compact3(Pm >> 1) + py, cz = 2 * compact3(Pm >> 2) + pz;
+    // the tile's 32 parents are consecutive in Morton order, a 4x4x2 block
+    // whose first parent is its lowest corner; lanes past the last parent
+    // (coarse levels) read the corner's sources and store nothing
+    const int64_t Pm0 = int64_t(t) * 32, Pm = Pm0 + i;
+    const int64_t Pl = Pm < nparent ? Pm : Pm0;
+    const int x0 = 2 * compact3(Pm0) + px, y0 = 2 * compact3(Pm0 >> 1) + py, z0 = 2 * compact3(Pm0 >> 2) + pz;
+    const int cx = 2 * compact3(Pl) + px, cy = 2 * compact3(Pl >> 1) + py, cz = 2 * compact3(Pl >> 2) + pz;
+    const float *phi0 =
+        phipad + (lv.pcell0[li] + (int64_t(z0 + kHalo) * P + (y0 + kHalo)) * P + (x0 + kHalo)) * NS;
+    const uint32_t voff = uint32_t((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + gh * KH) * 4u;
+    // this parity's list at this level, in LDS (entries read as uniform values)
+    __shared__ int stab[kListLen];
+    if (threadIdx.x < kListLen) stab[threadIdx.x] = mxtab[(level * 8 + p) * kListLen + threadIdx.x];
+    __syncthreads();
+    const char *kb = static_cast<const char *>(Kmx) + size_t(nb) * NBK * 64 * sizeof(BT);
+    const uint32_t boff = uint32_t(lane) * uint32_t(sizeof(BT));
 
-    float4 abuf[2][CH];
-    using BT = typename std::conditional<BF16, bf16x8, float4>::type;
-    constexpr int NBL = BF16 ? CH / 2 : CH;   // B loads per step
-    BT bbuf[2][NBL];
+    float4 abuf[NST][CH];
+    BT bbuf[NST][NBL];
 
     // Loads of step `step` (clamped, so that the loop body is branch free and
-    // the wait counts stay exact); a source outside the box (free space)
-    // reads a row of zeros.
+    // the wait counts stay exact).
     auto issue = [&](int step, auto bc) {
         constexpr int b = decltype(bc)::value;
         step = step < o_end * NCH ? step : o_end * NCH - 1;   // prefetch past the end
         const int oidx = step / NCH, ch = step - oidx * NCH;
-        const int pk = soff[oidx];
-        const int ox = (pk & 15) - 3, oy = ((pk >> 4) & 15) - 3, oz = (pk >> 8) - 3;
-        int sx = cx + ox, sy = cy + oy, sz = cz + oz;
-        bool valid = cvalid;
-        if constexpr (PERIODIC) {
-            sx &= D - 1;
-            sy &= D - 1;
-            sz &= D - 1;
-        } else {
-            valid = valid && sx >= 0 && sy >= 0 && sz >= 0 && sx < D && sy < D && sz < D;
-        }
-        const float *row = valid ? phi + (sx + int64_t(D) * (sy + int64_t(D) * sz)) * NS : zrow;
-        const float4 *ap = reinterpret_cast<const float4 *>(row + gh * KH) + ch * CH;
+        const int e = __builtin_amdgcn_readfirstlane(stab[oidx]);
+        const int oi = e & 511, delta = e >> 9;
+        const float4 *ap =
+            reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS) + voff) +
+            ch * CH;
 #pragma unroll
         for (int c = 0; c < CH; ++c) abuf[b][c] = ap[c];
-        const int oi = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
-        const BT *bp = reinterpret_cast<const BT *>(Kmx) + ((size_t(oi) * NB + nb) * (NA * 4 / (BF16 ? 8 : 4)) +
-                                                            ch * NBL) * 64 + lane;
+        const BT *bp = reinterpret_cast<const BT *>(kb + size_t(oi) * (NB * NBK * 64 * sizeof(BT)) + boff) +
+                       ch * NBL * 64;
 #pragma unroll
         for (int c = 0; c < NBL; ++c) bbuf[b][c] = bp[c * 64];
     };
 
-    floatx16 c0 = {}, c1 = {}, run = {};
-    // one k-chunk of one displacement from register stage b
-    auto compute = [&](auto bc) {
+    // Two accumulator pairs, alternating by displacement: the pair of
+    // displacement d is added to the running sums while the products of
+    // displacement d + 1 are under way, not after a drain of the matrix cores.
+    floatx16 ca0 = {}, ca1 = {}, cb0 = {}, cb1 = {}, run = {};
+    // one k-chunk of one displacement from register stage b into (x0, x1)
+    auto compute = [&](auto bc, floatx16 &x0, floatx16 &x1) {
         constexpr int b = decltype(bc)::value;
         if constexpr (!BF16) {
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const float4 a = abuf[b][c];
                 const float4 bb = bbuf[b][c];
-                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bb.x, c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bb.y, c1, 0, 0, 0);
-                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bb.z, c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bb.w, c1, 0, 0, 0);
+                x0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bb.x, x0, 0, 0, 0);
+                x1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bb.y, x1, 0, 0, 0);
+                x0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bb.z, x0, 0, 0, 0);
+                x1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bb.w, x1, 0, 0, 0);
             }
         } else {
 #pragma unroll
@@ -255,34 +300,46 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
                 a[5] = __bf16(a1.y);
                 a[6] = __bf16(a1.z);
                 a[7] = __bf16(a1.w);
-                if (c & 1) c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], c1, 0, 0, 0);
-                else c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], c0, 0, 0, 0);
+                if (c & 1) x1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], x1, 0, 0, 0);
+                else x0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], x0, 0, 0, 0);
             }
         }
     };
 
-    // Two displacements (2 * NCH steps) per trip, unrolled at compile time so
-    // that the register stage of every step is a constant and the body has
-    // no branches; the second displacement of the last trip is a clamped
-    // repeat whose sum is discarded.
+    // NST register stages: the loads of step s + NST - 1 are issued before the
+    // products of step s.  A trip covers TS steps, a multiple of NCH and NST
+    // holding an even number of displacements, unrolled at compile time so
+    // that the stage and accumulator pair of every step are constants and the
+    // body has no branches.
+    constexpr int TS0 = lcm_c(NCH, NST);
+    constexpr int TS = (TS0 / NCH) % 2 ? 2 * TS0 : TS0, TD = TS / NCH;
+    static_assert(OPS % TD == 0 && (OPS * NCH) % NST == 0, "pipeline trip");
     if (active) {
-        issue(o_begin * NCH, std::integral_constant<int, 0>{});
-        for (int op = o_begin; op < o_end; op += 2) {
-            static_for<0, 2 * NCH>([&](auto J) {
+        static_for<0, NST - 1>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            issue(o_begin * NCH + j, std::integral_constant<int, j>{});
+        });
+        for (int op = o_begin; op < o_end; op += TD) {
+            static_for<0, TS>([&](auto J) {
                 constexpr int j = decltype(J)::value;
-                constexpr int b = j & 1;
+                constexpr int b = j % NST;
                 constexpr int ch = j % NCH;
-                issue(op * NCH + j + 1, std::integral_constant<int, 1 - b>{});
-                // keep the loads of the next step ahead of this step's products
+                constexpr bool odd = (j / NCH) & 1;
+                issue(op * NCH + j + NST - 1, std::integral_constant<int, (j + NST - 1) % NST>{});
+                // keep the loads of the later steps ahead of this step's products
                 __builtin_amdgcn_sched_barrier(0);
-                if constexpr (ch == 0) {
-                    c0 = floatx16{};
-                    c1 = floatx16{};
+                if constexpr (odd) {
+                    if constexpr (ch == 0) cb0 = cb1 = floatx16{};
+                    compute(std::integral_constant<int, b>{}, cb0, cb1);
+                    if constexpr (ch == 0) run += ca0 + ca1;
+                } else {
+                    if constexpr (ch == 0) ca0 = ca1 = floatx16{};
+                    compute(std::integral_constant<int, b>{}, ca0, ca1);
+                    if constexpr (ch == 0) run += cb0 + cb1;
                 }
-                compute(std::integral_constant<int, b>{});
-                if constexpr (ch == NCH - 1) run += c0 + c1;
             });
         }
+        run += cb0 + cb1;   // the last displacement (TD is even)
     }
     if constexpr (NSPLIT > 1) {
         __shared__ floatx16 red[NSPLIT - 1][TPW][64];
@@ -301,7 +358,7 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int ii = 4 * (lane >> 5) + (r & 3) + 8 * (r >> 2);
-        const int64_t P2 = int64_t(t) * 32 + ii;
+        const int64_t P2 = Pm0 + ii;
         if (P2 >= nparent) continue;
         const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
         const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
@@ -312,14 +369,13 @@ __global__ void __launch_bounds__(256) k_m2l_mx(Geom g, const void *__restrict__
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 // Double precision on the matrix cores (v_mfma_f64_16x16x4f64): a wave owns
-// 16 target cells of one parity (16 parents consecutive in Morton order) and
-// 16 target nodes; the source axis is split in four quarters, one per
-// quarter wave.  Same pipelining as the float kernel.
-template <int N, int CH, bool PERIODIC>
-__global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restrict__ Kmx,
-                                                 const signed char *__restrict__ offs, MxLevels lv,
-                                                 const double *__restrict__ phi_all,
-                                                 const double *__restrict__ zrow,
+// 16 target cells of one parity (16 parents consecutive in Morton order, a
+// 4x2x2 block) and 16 target nodes; the source axis is split in four
+// quarters, one per quarter wave.  Same addressing and pipelining as the
+// float kernel.
+template <int N, int CH>
+__global__ void __launch_bounds__(256) k_m2l_f64(const double2 *__restrict__ Kmx, const int *__restrict__ mxtab,
+                                                 MxLevels lv, const double *__restrict__ phipad,
                                                  double *__restrict__ loc_all, int nwg)
 {
     constexpr int N3 = N * N * N, NS = (N3 + 15) & ~15, KQ = NS / 4, NB = (N3 + 15) / 16;
@@ -334,27 +390,28 @@ __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restri
     wg -= lv.wg_begin[li];
     const int level = lv.level[li], ntile = lv.ntile[li];
     const double inv_side = lv.inv_side64[li];
-    const double *phi = phi_all + lv.cell0[li] * NS;
     double *loc = loc_all + lv.cell0[li] * NS;
     const int ntg = (ntile + 3) >> 2;
     const int tg = wg % ntg, pn = wg / ntg;
     const int nb = pn % NB, p = pn / NB;
     const int lane = threadIdx.x & 63;
-    const int t = tg * 4 + (threadIdx.x >> 6);
-    __shared__ int soff[kListLen];
-    if (threadIdx.x < kListLen) {
-        const signed char *q = offs + (p * kListLen + threadIdx.x) * 3;
-        soff[threadIdx.x] = (q[0] + 3) | ((q[1] + 3) << 4) | ((q[2] + 3) << 8);
-    }
+    const int t = tg * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ int stab[kListLen];
+    if (threadIdx.x < kListLen) stab[threadIdx.x] = mxtab[(level * 8 + p) * kListLen + threadIdx.x];
     __syncthreads();
     if (t >= ntile) return;
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
-    const int D = 1 << level, Dp = D >> 1;
+    const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
     const int i = lane & 15, gq = lane >> 4;
-    const int64_t Pm = int64_t(t) * 16 + i;
-    const bool cvalid = Pm < nparent;
-    const int cx = 2 * compact3(Pm) + px, cy = 2 * compact3(Pm >> 1) + py, cz = 2 * compact3(Pm >> 2) + pz;
+    const int64_t Pm0 = int64_t(t) * 16, Pm = Pm0 + i;
+    const int64_t Pl = Pm < nparent ? Pm : Pm0;
+    const int x0 = 2 * compact3(Pm0) + px, y0 = 2 * compact3(Pm0 >> 1) + py, z0 = 2 * compact3(Pm0 >> 2) + pz;
+    const int cx = 2 * compact3(Pl) + px, cy = 2 * compact3(Pl >> 1) + py, cz = 2 * compact3(Pl >> 2) + pz;
+    const double *phi0 =
+        phipad + (lv.pcell0[li] + (int64_t(z0 + kHalo) * P + (y0 + kHalo)) * P + (x0 + kHalo)) * NS;
+    const uint32_t voff = uint32_t((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + gq * KQ) * 8u;
+    const double2 *kb = Kmx + size_t(nb) * NA * 64 + lane;
     double2 abuf[2][CH], bbuf[2][CH];
 
     auto issue = [&](int step, auto bc) {
@@ -362,23 +419,14 @@ __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restri
         constexpr int nsteps = kListLen * NCH;
         step = step < nsteps ? step : nsteps - 1;
         const int oidx = step / NCH, ch = step - oidx * NCH;
-        const int pk = soff[oidx];
-        const int ox = (pk & 15) - 3, oy = ((pk >> 4) & 15) - 3, oz = (pk >> 8) - 3;
-        int sx = cx + ox, sy = cy + oy, sz = cz + oz;
-        bool valid = cvalid;
-        if constexpr (PERIODIC) {
-            sx &= D - 1;
-            sy &= D - 1;
-            sz &= D - 1;
-        } else {
-            valid = valid && sx >= 0 && sy >= 0 && sz >= 0 && sx < D && sy < D && sz < D;
-        }
-        const double *row = valid ? phi + (sx + int64_t(D) * (sy + int64_t(D) * sz)) * NS : zrow;
-        const double2 *ap = reinterpret_cast<const double2 *>(row + gq * KQ) + ch * CH;
+        const int e = __builtin_amdgcn_readfirstlane(stab[oidx]);
+        const int oi = e & 511, delta = e >> 9;
+        const double2 *ap =
+            reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS) + voff) +
+            ch * CH;
 #pragma unroll
         for (int c = 0; c < CH; ++c) abuf[b][c] = ap[c];
-        const int oi = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
-        const double2 *bp = Kmx + ((size_t(oi) * NB + nb) * NA + ch * CH) * 64 + lane;
+        const double2 *bp = kb + (size_t(oi) * NB * NA + ch * CH) * 64;
 #pragma unroll
         for (int c = 0; c < CH; ++c) bbuf[b][c] = bp[c * 64];
     };
@@ -410,7 +458,7 @@ __global__ void __launch_bounds__(256) k_m2l_f64(Geom g, const double2 *__restri
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ii = (lane >> 4) + 4 * r;
-        const int64_t P2 = int64_t(t) * 16 + ii;
+        const int64_t P2 = Pm0 + ii;
         if (P2 >= nparent) continue;
         const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
         const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
@@ -443,8 +491,8 @@ double il_pairs(const Geom &g, int level)
 
 // Level table: tiles of `cells_per_tile` parents per (parity, node block),
 // `tpw` tiles per workgroup.
-int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, int cells_per_tile, int nb, int tpw,
-                MxLevels &lv)
+int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int cells_per_tile,
+                int nb, int tpw, MxLevels &lv)
 {
     lv.nlev = lmax - lmin + 1;
     int wgs = 0;
@@ -457,6 +505,7 @@ int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, int cells
         lv.wg_begin[i] = wgs;
         wgs += 8 * nb * ((lv.ntile[i] + tpw - 1) / tpw);
         lv.cell0[i] = lvl[l];
+        lv.pcell0[i] = plvl[l];
         lv.inv_side[i] = float(double(1 << l) / g.box);
         lv.inv_side64[i] = double(1 << l) / g.box;
     }
@@ -465,20 +514,22 @@ int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, int cells
 }
 
 // k-chunk per pipeline step (float4 loads of A and of B per lane): 4 for
-// n <= 4, where more resident waves pay off, 8 above (measured)
+// n <= 4, where more resident waves pay off, 8 above (measured); NST
+// register stages, deep enough to cover reads that miss L2
 template <int N> struct MxChunk {
     static constexpr int NA = MxShape<N>::KH / 4;
     static constexpr int CH = N <= 4 ? (NA % 4 == 0 ? 4 : NA) : (NA % 8 == 0 ? 8 : (NA % 4 == 0 ? 4 : NA));
+    static constexpr int NST = N <= 4 ? 2 : 4;
 };
 
 template <int N>
-int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const float *phi, const float *zrow,
+int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const float *phipad,
               float *loc, hipStream_t st)
 {
     using S = MxShape<N>;
     constexpr int CH = MxChunk<N>::CH;
     const Geom &g = plan->g;
-    const signed char *offs = static_cast<const signed char *>(plan->ops.offs);
+    const int *tab = plan->ops.mxtab;
     // waves per tile: enough waves to keep every SIMD busy
     int64_t tiles = 0;
     for (int l = lmin; l <= lmax; ++l) {
@@ -494,19 +545,17 @@ int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const fl
     auto go = [&](int l0, int l1, bool use_bf) -> int {
         if (l0 > l1) return EQFMM_OK;
         MxLevels lv;
-        const int nwg = fill_levels(g, l0, l1, lvl, 32, S::NB, 4 / split, lv);
+        const int nwg = fill_levels(g, l0, l1, lvl, plvl, 32, S::NB, 4 / split, lv);
         const int grid = (nwg + 7) & ~7;
         const void *K = use_bf ? Kbf : plan->ops.Kmx;
-#define EQ_M2L_LAUNCH(B, P, SP) \
-    k_m2l_mx<N, B, CH, P, SP><<<grid, 256, 0, st>>>(g, K, offs, lv, phi, zrow, loc, nwg)
-#define EQ_M2L_SPLIT(B, P)                           \
-    if (split == 1) EQ_M2L_LAUNCH(B, P, 1);          \
-    else if (split == 2) EQ_M2L_LAUNCH(B, P, 2);     \
-    else EQ_M2L_LAUNCH(B, P, 4);
-        if (use_bf && g.periodic) { EQ_M2L_SPLIT(true, true) }
-        else if (use_bf) { EQ_M2L_SPLIT(true, false) }
-        else if (g.periodic) { EQ_M2L_SPLIT(false, true) }
-        else { EQ_M2L_SPLIT(false, false) }
+#define EQ_M2L_LAUNCH(B, SP) \
+    k_m2l_mx<N, B, CH, SP, MxChunk<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg)
+#define EQ_M2L_SPLIT(B)                          \
+    if (split == 1) EQ_M2L_LAUNCH(B, 1);         \
+    else if (split == 2) EQ_M2L_LAUNCH(B, 2);    \
+    else EQ_M2L_LAUNCH(B, 4);
+        if (use_bf) { EQ_M2L_SPLIT(true) }
+        else { EQ_M2L_SPLIT(false) }
 #undef EQ_M2L_SPLIT
 #undef EQ_M2L_LAUNCH
         return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
@@ -518,32 +567,71 @@ int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const fl
 }
 
 template <int N>
-int launch_f64(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const double *phi, const double *zrow,
-               double *loc, hipStream_t st)
+int launch_f64(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl,
+               const double *phipad, double *loc, hipStream_t st)
 {
     constexpr int NA = ((N * N * N + 15) & ~15) / 8;
     constexpr int CH = NA % 4 == 0 ? 4 : (NA % 2 == 0 ? 2 : 1);
     constexpr int NB = (N * N * N + 15) / 16;
     const Geom &g = plan->g;
     MxLevels lv;
-    const int nwg = fill_levels(g, lmin, lmax, lvl, 16, NB, 4, lv);
+    const int nwg = fill_levels(g, lmin, lmax, lvl, plvl, 16, NB, 4, lv);
     const int grid = (nwg + 7) & ~7;
     const double2 *K = static_cast<const double2 *>(plan->ops.Kmx);
-    const signed char *offs = static_cast<const signed char *>(plan->ops.offs);
-    if (g.periodic)
-        k_m2l_f64<N, CH, true><<<grid, 256, 0, st>>>(g, K, offs, lv, phi, zrow, loc, nwg);
-    else
-        k_m2l_f64<N, CH, false><<<grid, 256, 0, st>>>(g, K, offs, lv, phi, zrow, loc, nwg);
+    k_m2l_f64<N, CH><<<grid, 256, 0, st>>>(K, plan->ops.mxtab, lv, phipad, loc, nwg);
+    return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+}
+
+template <typename R, int N>
+int launch_pad_n(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const R *phi,
+                 R *phipad, hipStream_t st)
+{
+    using V = typename std::conditional<sizeof(R) == sizeof(float), float4, double2>::type;
+    constexpr int VPR = MxShape<N>::NS * int(sizeof(R)) / 16;
+    MxPad pd;
+    pd.nlev = lmax - lmin + 1;
+    int64_t rows = 0;
+    for (int i = 0; i < pd.nlev; ++i) {
+        const int l = lmin + i;
+        const int64_t P = (int64_t(1) << l) + 2 * kHalo;
+        pd.level[i] = l;
+        pd.row0[i] = rows;
+        pd.src0[i] = lvl[l];
+        pd.dst0[i] = plvl[l];
+        rows += P * P * P;
+    }
+    pd.row0[pd.nlev] = rows;
+    const int64_t blocks = (rows * VPR + 255) / 256;
+    k_m2l_pad<V, VPR><<<dim3(unsigned(blocks)), 256, 0, st>>>(pd, g.periodic, reinterpret_cast<const V *>(phi),
+                                                             reinterpret_cast<V *>(phipad));
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
 
 }  // namespace
 
+// The haloed copy of Phi at the interaction levels lmin..lmax.
+template <typename R>
+int launch_m2l_pad(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const R *phi,
+                   R *phipad, hipStream_t st)
+{
+    const Geom &g = plan->g;
+    if (lmax - lmin + 1 > 10 || lmin > lmax) return EQFMM_EINVAL;
+    switch (g.n) {
+        case 2: return launch_pad_n<R, 2>(g, lmin, lmax, lvl, plvl, phi, phipad, st);
+        case 3: return launch_pad_n<R, 3>(g, lmin, lmax, lvl, plvl, phi, phipad, st);
+        case 4: return launch_pad_n<R, 4>(g, lmin, lmax, lvl, plvl, phi, phipad, st);
+        case 5: return launch_pad_n<R, 5>(g, lmin, lmax, lvl, plvl, phi, phipad, st);
+        case 6: return launch_pad_n<R, 6>(g, lmin, lmax, lvl, plvl, phi, phipad, st);
+        case 7: return launch_pad_n<R, 7>(g, lmin, lmax, lvl, plvl, phi, phipad, st);
+        default: return EQFMM_EINVAL;
+    }
+}
+
 // All interaction levels lmin..lmax in one launch (two for the bf16 mode);
 // each writes (stores) its level's local vectors.
 template <typename R>
-int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const R *phi, const R *zrow, R *loc,
-               hipStream_t st)
+int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const R *phipad,
+               R *loc, hipStream_t st)
 {
     const Geom &g = plan->g;
     const int pk = prof_begin_m2l(plan, st);
@@ -551,9 +639,9 @@ int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const R
 #define EQ_CASE(NN)                                                                          \
     case NN:                                                                                 \
         if constexpr (sizeof(R) == sizeof(float))                                            \
-            rc = launch_mx<NN>(plan, lmin, lmax, lvl, phi, zrow, loc, st);                   \
+            rc = launch_mx<NN>(plan, lmin, lmax, lvl, plvl, phipad, loc, st);                \
         else                                                                                 \
-            rc = launch_f64<NN>(plan, lmin, lmax, lvl, phi, zrow, loc, st);                  \
+            rc = launch_f64<NN>(plan, lmin, lmax, lvl, plvl, phipad, loc, st);               \
         break;
     switch (g.n) {
         EQ_CASE(2) EQ_CASE(3) EQ_CASE(4) EQ_CASE(5) EQ_CASE(6) EQ_CASE(7)
@@ -569,9 +657,13 @@ int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const R
     return rc;
 }
 
-template int launch_m2l<float>(eqfmm_plan *, int, int, const int64_t *, const float *, const float *, float *,
+template int launch_m2l_pad<float>(eqfmm_plan *, int, int, const int64_t *, const int64_t *, const float *, float *,
+                                   hipStream_t);
+template int launch_m2l_pad<double>(eqfmm_plan *, int, int, const int64_t *, const int64_t *, const double *,
+                                    double *, hipStream_t);
+template int launch_m2l<float>(eqfmm_plan *, int, int, const int64_t *, const int64_t *, const float *, float *,
                                hipStream_t);
-template int launch_m2l<double>(eqfmm_plan *, int, int, const int64_t *, const double *, const double *,
+template int launch_m2l<double>(eqfmm_plan *, int, int, const int64_t *, const int64_t *, const double *,
                                 double *, hipStream_t);
 
 }  // namespace eqfmm

@@ -165,18 +165,21 @@ int build_image(eqfmm_plan *plan)
     plan->off_K = take(rs * h.K.size());
     plan->off_T = take(rs * std::max<size_t>(h.T.size(), 1));
     plan->off_Kmx = take(std::max<size_t>(mx_layout_bytes(g, prec), 1));
-    plan->off_offs = take(8 * kListLen * 3);
+    plan->off_mxtab = take(sizeof(int32_t) * (g.L + 1) * 8 * kListLen);
     plan->image.assign(off, 0);
     // interaction list of a cell with parity p (cell index mod 2 per axis):
     // displacements in [-2-p, 3-p]^3 that are not adjacent.  The list is
     // ordered by the parity of the displacement: all targets of one parity
     // then read sources of a single parity class for ~24 consecutive
     // displacements, a set that stays in L2.  The 189 entries are padded to
-    // kListLen with the displacement (0,0,0), whose matrix is zero.
+    // kListLen with the displacement (0,0,0), whose matrix is zero.  Each
+    // entry is stored per level as the row distance in that level's haloed
+    // layout (side 2^l + 2 kHalo) and the matrix index.
     {
-        signed char *o = reinterpret_cast<signed char *>(plan->image.data() + plan->off_offs);
+        int32_t *tab = reinterpret_cast<int32_t *>(plan->image.data() + plan->off_mxtab);
         for (int p = 0; p < 8; ++p) {
             const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+            int ox_[kListLen] = {}, oy_[kListLen] = {}, oz_[kListLen] = {};
             int m = 0;
             for (int q = 0; q < 8; ++q)
                 for (int oz = -2 - pz; oz <= 3 - pz; ++oz)
@@ -184,13 +187,19 @@ int build_image(eqfmm_plan *plan)
                         for (int ox = -2 - px; ox <= 3 - px; ++ox) {
                             if (std::abs(ox) <= 1 && std::abs(oy) <= 1 && std::abs(oz) <= 1) continue;
                             if (((ox & 1) | ((oy & 1) << 1) | ((oz & 1) << 2)) != q) continue;
-                            o[(p * kListLen + m) * 3 + 0] = static_cast<signed char>(ox);
-                            o[(p * kListLen + m) * 3 + 1] = static_cast<signed char>(oy);
-                            o[(p * kListLen + m) * 3 + 2] = static_cast<signed char>(oz);
+                            ox_[m] = ox;
+                            oy_[m] = oy;
+                            oz_[m] = oz;
                             ++m;
                         }
-            for (; m < kListLen; ++m) o[(p * kListLen + m) * 3 + 0] = o[(p * kListLen + m) * 3 + 1] =
-                                          o[(p * kListLen + m) * 3 + 2] = 0;
+            for (int l = 0; l <= g.L; ++l) {
+                const int64_t P = (int64_t(1) << l) + 2 * kHalo;
+                for (int k = 0; k < kListLen; ++k) {
+                    const int64_t delta = (oz_[k] * P + oy_[k]) * P + ox_[k];
+                    const int oi = (ox_[k] + 3) + 7 * (oy_[k] + 3) + 49 * (oz_[k] + 3);
+                    tab[(l * 8 + p) * kListLen + k] = int32_t(delta * 512 + oi);
+                }
+            }
         }
     }
     auto &img = plan->image;
@@ -254,7 +263,19 @@ WsLayout ws_layout(const eqfmm_plan *plan, int64_t n)
     // split axis the force is a short sum of large cancelling terms
     W.gw = take(sizeof(double) * W.fcap);
     W.gdw = take(sizeof(double) * 3 * W.fcap);
-    W.phi = take(rs * (ncells + 1) * g.ns);   // + one row of zeros
+    W.phi = take(rs * ncells * g.ns);
+    // the interaction levels again, each inside a halo of kHalo cells (zeros
+    // in free space, periodic images otherwise): the far-field kernels read
+    // every source of a displacement at one fixed row distance
+    W.plvl.assign(g.L + 2, 0);
+    int64_t pcells = 0;
+    for (int l = g.periodic ? 1 : 2; l <= g.L; ++l) {
+        const int64_t P = (int64_t(1) << l) + 2 * kHalo;
+        W.plvl[l] = pcells;
+        pcells += P * P * P;
+    }
+    W.plvl[g.L + 1] = pcells;
+    W.phipad = take(rs * pcells * g.ns);
     W.loc = take(rs * ncells * g.ns);
     W.sphi = take(sizeof(double) * W.fcap);
     W.sfld = take(rs * 3 * W.fcap);
@@ -347,7 +368,7 @@ int eqfmm_plan_upload(eqfmm_plan *plan, void *dev_buf, size_t bytes, void *strea
     plan->ops.K = b + plan->off_K;
     plan->ops.T = b + plan->off_T;
     plan->ops.Kmx = b + plan->off_Kmx;
-    plan->ops.offs = b + plan->off_offs;
+    plan->ops.mxtab = reinterpret_cast<const int *>(b + plan->off_mxtab);
     return EQFMM_OK;
 }
 
