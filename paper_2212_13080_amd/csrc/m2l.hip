@@ -172,10 +172,10 @@ __global__ void __launch_bounds__(256) k_m2l_pad(MxPad pd, int periodic, const V
 
 // --------------------------------------------------------------- kernels
 
-// grid: round_up(8 * NB * ceil(ntile / 4), 8) workgroups of 4 waves; the
-// workgroup id is remapped so that each of the 8 XCDs gets a contiguous
-// range of (parity, node block, tile) work, i.e. mostly one parity and
-// hence one set of 189 matrices in its L2.
+// grid: round_up(8 * ceil(NB * ntile / TPW), 8) workgroups of 4 waves per
+// level; the workgroup id is remapped so that each of the 8 XCDs gets a
+// contiguous range of (parity, tile, node block) work, i.e. mostly one
+// parity and hence one set of 189 matrices in its L2.
 //
 // Sources are read from the haloed copy of Phi, where the source of every
 // target of a tile lies at the same row distance for a given displacement:
@@ -210,23 +210,26 @@ __global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, co
     const int level = lv.level[li], ntile = lv.ntile[li];
     const float inv_side = lv.inv_side[li];
     float *loc = loc_all + lv.cell0[li] * NS;
-    // a workgroup of 4 waves holds TPW = 4 / NSPLIT tiles; NSPLIT waves share
-    // one tile, each running a contiguous part of the interaction list, and
-    // their sums are added in a fixed order at the end
+    // a workgroup of 4 waves holds TPW = 4 / NSPLIT work items (tile, node
+    // block), node block fastest: the node blocks of a tile then read its
+    // sources at the same time.  NSPLIT waves share one item, each running a
+    // contiguous part of the interaction list, and their sums are added in a
+    // fixed order at the end.
     constexpr int TPW = 4 / NSPLIT;
-    const int ntg = (ntile + TPW - 1) / TPW;
-    const int tg = wg % ntg, pn = wg / ntg;
-    const int nb = pn % NB, p = pn / NB;
+    const int nitem = ntile * NB;
+    const int ngrp = (nitem + TPW - 1) / TPW;
+    const int grp = wg % ngrp, p = wg / ngrp;
     const int lane = threadIdx.x & 63;
     // wave index as a uniform value: the tile, list range and addresses
     // derived from it then live in scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tg * TPW + wv % TPW;
+    const int it = grp * TPW + wv % TPW;
+    const int t = it / NB, nb = it - t * NB;
     const int hs = wv / TPW;
     constexpr int OPS = kListLen / NSPLIT;           // even: displacements go in pairs
     static_assert(kListLen % (2 * NSPLIT) == 0, "list padding");
     const int o_begin = hs * OPS, o_end = o_begin + OPS;
-    const bool active = t < ntile;
+    const bool active = it < nitem;
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
     const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
@@ -391,15 +394,17 @@ __global__ void __launch_bounds__(256) k_m2l_f64(const double2 *__restrict__ Kmx
     const int level = lv.level[li], ntile = lv.ntile[li];
     const double inv_side = lv.inv_side64[li];
     double *loc = loc_all + lv.cell0[li] * NS;
-    const int ntg = (ntile + 3) >> 2;
-    const int tg = wg % ntg, pn = wg / ntg;
-    const int nb = pn % NB, p = pn / NB;
+    // 4 work items (tile, node block) per workgroup, node block fastest
+    const int nitem = ntile * NB;
+    const int ngrp = (nitem + 3) >> 2;
+    const int grp = wg % ngrp, p = wg / ngrp;
     const int lane = threadIdx.x & 63;
-    const int t = tg * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int it = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = it / NB, nb = it - t * NB;
     __shared__ int stab[kListLen];
     if (threadIdx.x < kListLen) stab[threadIdx.x] = mxtab[(level * 8 + p) * kListLen + threadIdx.x];
     __syncthreads();
-    if (t >= ntile) return;
+    if (it >= nitem) return;
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
     const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
@@ -489,8 +494,8 @@ double il_pairs(const Geom &g, int level)
     return double(A) * A * A - double(B) * B * B;
 }
 
-// Level table: tiles of `cells_per_tile` parents per (parity, node block),
-// `tpw` tiles per workgroup.
+// Level table: tiles of `cells_per_tile` parents per parity, `nb` node
+// blocks per tile, `tpw` (tile, node block) items per workgroup.
 int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int cells_per_tile,
                 int nb, int tpw, MxLevels &lv)
 {
@@ -503,7 +508,7 @@ int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int
         lv.level[i] = l;
         lv.ntile[i] = int((nparent + cells_per_tile - 1) / cells_per_tile);
         lv.wg_begin[i] = wgs;
-        wgs += 8 * nb * ((lv.ntile[i] + tpw - 1) / tpw);
+        wgs += 8 * ((lv.ntile[i] * nb + tpw - 1) / tpw);
         lv.cell0[i] = lvl[l];
         lv.pcell0[i] = plvl[l];
         lv.inv_side[i] = float(double(1 << l) / g.box);
