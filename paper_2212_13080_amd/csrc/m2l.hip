@@ -172,10 +172,12 @@ __global__ void __launch_bounds__(256) k_m2l_pad(MxPad pd, int periodic, const V
 
 // --------------------------------------------------------------- kernels
 
-// grid: round_up(8 * ceil(NB * ntile / TPW), 8) workgroups of 4 waves per
-// level; the workgroup id is remapped so that each of the 8 XCDs gets a
-// contiguous range of (parity, tile, node block) work, i.e. mostly one
-// parity and hence one set of 189 matrices in its L2.
+// grid: ceil(8 * NB * ntile / TPW) workgroups of 4 waves per level (rounded
+// up to 8 overall); work items (tile, parity, node block) are numbered with
+// the node block fastest and the tile slowest, and the workgroup id is
+// remapped so that each of the 8 XCDs gets a contiguous range of them: a
+// compact region of space whose targets of all parities share their
+// sources in that XCD's L2.
 //
 // Sources are read from the haloed copy of Phi, where the source of every
 // target of a tile lies at the same row distance for a given displacement:
@@ -216,15 +218,14 @@ __global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, co
     // contiguous part of the interaction list, and their sums are added in a
     // fixed order at the end.
     constexpr int TPW = 4 / NSPLIT;
-    const int nitem = ntile * NB;
-    const int ngrp = (nitem + TPW - 1) / TPW;
-    const int grp = wg % ngrp, p = wg / ngrp;
+    const int nitem = ntile * 8 * NB;
     const int lane = threadIdx.x & 63;
     // wave index as a uniform value: the tile, list range and addresses
     // derived from it then live in scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int it = grp * TPW + wv % TPW;
-    const int t = it / NB, nb = it - t * NB;
+    const int it = wg * TPW + wv % TPW;
+    const int tp = it / NB, nb = it - tp * NB;
+    const int t = tp >> 3, p = tp & 7;
     const int hs = wv / TPW;
     constexpr int OPS = kListLen / NSPLIT;           // even: displacements go in pairs
     static_assert(kListLen % (2 * NSPLIT) == 0, "list padding");
@@ -244,10 +245,12 @@ __global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, co
     const float *phi0 =
         phipad + (lv.pcell0[li] + (int64_t(z0 + kHalo) * P + (y0 + kHalo)) * P + (x0 + kHalo)) * NS;
     const uint32_t voff = uint32_t((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + gh * KH) * 4u;
-    // this parity's list at this level, in LDS (entries read as uniform values)
-    __shared__ int stab[kListLen];
-    if (threadIdx.x < kListLen) stab[threadIdx.x] = mxtab[(level * 8 + p) * kListLen + threadIdx.x];
+    // the lists of the 8 parities at this level, in LDS (entries read as
+    // uniform values)
+    __shared__ int stab[8 * kListLen];
+    for (int k = threadIdx.x; k < 8 * kListLen; k += 256) stab[k] = mxtab[level * 8 * kListLen + k];
     __syncthreads();
+    const int *ptab = stab + p * kListLen;
     const char *kb = static_cast<const char *>(Kmx) + size_t(nb) * NBK * 64 * sizeof(BT);
     const uint32_t boff = uint32_t(lane) * uint32_t(sizeof(BT));
 
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, co
         constexpr int b = decltype(bc)::value;
         step = step < o_end * NCH ? step : o_end * NCH - 1;   // prefetch past the end
         const int oidx = step / NCH, ch = step - oidx * NCH;
-        const int e = __builtin_amdgcn_readfirstlane(stab[oidx]);
+        const int e = __builtin_amdgcn_readfirstlane(ptab[oidx]);
         const int oi = e & 511, delta = e >> 9;
         const float4 *ap =
             reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS) + voff) +
@@ -394,17 +397,17 @@ __global__ void __launch_bounds__(256) k_m2l_f64(const double2 *__restrict__ Kmx
     const int level = lv.level[li], ntile = lv.ntile[li];
     const double inv_side = lv.inv_side64[li];
     double *loc = loc_all + lv.cell0[li] * NS;
-    // 4 work items (tile, node block) per workgroup, node block fastest
-    const int nitem = ntile * NB;
-    const int ngrp = (nitem + 3) >> 2;
-    const int grp = wg % ngrp, p = wg / ngrp;
+    // 4 work items (tile, parity, node block) per workgroup, node block fastest
+    const int nitem = ntile * 8 * NB;
     const int lane = threadIdx.x & 63;
-    const int it = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = it / NB, nb = it - t * NB;
-    __shared__ int stab[kListLen];
-    if (threadIdx.x < kListLen) stab[threadIdx.x] = mxtab[(level * 8 + p) * kListLen + threadIdx.x];
+    const int it = wg * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tp = it / NB, nb = it - tp * NB;
+    const int t = tp >> 3, p = tp & 7;
+    __shared__ int stab[8 * kListLen];
+    for (int k = threadIdx.x; k < 8 * kListLen; k += 256) stab[k] = mxtab[level * 8 * kListLen + k];
     __syncthreads();
     if (it >= nitem) return;
+    const int *ptab = stab + p * kListLen;
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
     const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
@@ -424,7 +427,7 @@ __global__ void __launch_bounds__(256) k_m2l_f64(const double2 *__restrict__ Kmx
         constexpr int nsteps = kListLen * NCH;
         step = step < nsteps ? step : nsteps - 1;
         const int oidx = step / NCH, ch = step - oidx * NCH;
-        const int e = __builtin_amdgcn_readfirstlane(stab[oidx]);
+        const int e = __builtin_amdgcn_readfirstlane(ptab[oidx]);
         const int oi = e & 511, delta = e >> 9;
         const double2 *ap =
             reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS) + voff) +
@@ -494,8 +497,8 @@ double il_pairs(const Geom &g, int level)
     return double(A) * A * A - double(B) * B * B;
 }
 
-// Level table: tiles of `cells_per_tile` parents per parity, `nb` node
-// blocks per tile, `tpw` (tile, node block) items per workgroup.
+// Level table: tiles of `cells_per_tile` parents, 8 parities and `nb` node
+// blocks per tile, `tpw` (tile, parity, node block) items per workgroup.
 int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int cells_per_tile,
                 int nb, int tpw, MxLevels &lv)
 {
@@ -508,7 +511,7 @@ int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int
         lv.level[i] = l;
         lv.ntile[i] = int((nparent + cells_per_tile - 1) / cells_per_tile);
         lv.wg_begin[i] = wgs;
-        wgs += 8 * ((lv.ntile[i] * nb + tpw - 1) / tpw);
+        wgs += (lv.ntile[i] * 8 * nb + tpw - 1) / tpw;
         lv.cell0[i] = lvl[l];
         lv.pcell0[i] = plvl[l];
         lv.inv_side[i] = float(double(1 << l) / g.box);
