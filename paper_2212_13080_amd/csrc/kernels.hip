@@ -188,34 +188,69 @@ __device__ __forceinline__ void axis_pieces(const Geom &g, const double *seg, co
     P.cnt = m;
 }
 
+// Finest cell along one axis and whether the charge is split there (the
+// same test as axis_pieces, without the pieces).
+__device__ __forceinline__ bool axis_split(const Geom &g, double v, int &c)
+{
+    const double s = g.s_leaf, d = g.d;
+    c = int(floor(v / s));
+    c = c < 0 ? 0 : (c >= g.D ? g.D - 1 : c);
+    if (!g.continuous) return false;
+    const double dlo = v - c * s, dhi = (c + 1) * s - v;
+    return (dlo < d && (g.periodic || c > 0)) || (dhi < d && (g.periodic || c < g.D - 1));
+}
+
 // ------------------------------------------------------------ a1/a2: bin
+
+// Clears the header, the per-cell counts and the cursors of one forward.
+__global__ void __launch_bounds__(256) k_clear(WsHeader *hdr, int *leafcnt, int *cursor, int64_t nleaf)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i <= nleaf) leafcnt[i] = 0;
+    if (i < nleaf) cursor[i] = 0;
+    if (i == 0) *hdr = WsHeader{};
+}
 
 template <int N>
 __global__ void __launch_bounds__(256) k_count(Geom g, const double *seg, int64_t n,
-                                               const double *pos, const double *q, int *cnt,
+                                               const double *pos, const double *q, int *cnt, int *fstart,
                                                unsigned char *smask, int *leafcnt, WsHeader *hdr)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double qs = 0.0, qa = 0.0;
     if (i < n) {
-        Pieces<N> P[3];
         int flags = 0;
+        double v[3];
+        int c[3];
+        bool split = false;
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double v;
-            flags |= box_coord(g, pos[3 * i + a], a, v);
-            axis_pieces<N, false>(g, seg, nullptr, v, P[a]);
+            flags |= box_coord(g, pos[3 * i + a], a, v[a]);
+            split |= axis_split(g, v[a], c[a]);
         }
         const double qi = q[i];
         if (!isfinite(qi)) flags |= 2;
-        cnt[i] = P[0].cnt * P[1].cnt * P[2].cnt;
-        smask[i] = (P[0].cnt > 1) | ((P[1].cnt > 1) << 1) | ((P[2].cnt > 1) << 2);
-        for (int kz = 0; kz < P[2].cnt; ++kz)
-            for (int ky = 0; ky < P[1].cnt; ++ky)
-                for (int kx = 0; kx < P[0].cnt; ++kx) {
-                    const int64_t leaf =
-                        P[0].cell[kx] + int64_t(g.D) * (P[1].cell[ky] + int64_t(g.D) * P[2].cell[kz]);
-                    atomicAdd(&leafcnt[leaf], 1);
-                }
+        if (!split) {   // one piece, in cell c (every charge of the unsplit modes)
+            if (g.continuous) cnt[i] = 1;
+            else {
+                fstart[i] = int(i);   // one fragment per charge: the prefix sums are the identity
+                if (i == n - 1) fstart[n] = int(n);
+            }
+            smask[i] = 0;
+            atomicAdd(&leafcnt[c[0] + int64_t(g.D) * (c[1] + int64_t(g.D) * c[2])], 1);
+        } else {
+            Pieces<N> P[3];
+            for (int a = 0; a < 3; ++a) axis_pieces<N, false>(g, seg, nullptr, v[a], P[a]);
+            cnt[i] = P[0].cnt * P[1].cnt * P[2].cnt;
+            smask[i] = (P[0].cnt > 1) | ((P[1].cnt > 1) << 1) | ((P[2].cnt > 1) << 2);
+            for (int kz = 0; kz < P[2].cnt; ++kz)
+                for (int ky = 0; ky < P[1].cnt; ++ky)
+                    for (int kx = 0; kx < P[0].cnt; ++kx) {
+                        const int64_t leaf =
+                            P[0].cell[kx] + int64_t(g.D) * (P[1].cell[ky] + int64_t(g.D) * P[2].cell[kz]);
+                        atomicAdd(&leafcnt[leaf], 1);
+                    }
+        }
         if (flags) atomicOr(&hdr->flags, flags);
         if (isfinite(qi)) {
             qs = qi;
@@ -250,14 +285,35 @@ __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const d
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Pieces<N> P[3];
+    double v[3];
+    int c[3];
+    bool split = false;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double v;
-        box_coord(g, pos[3 * i + a], a, v);
-        axis_pieces<N, true>(g, seg, segden, v, P[a]);
+        box_coord(g, pos[3 * i + a], a, v[a]);
+        split |= axis_split(g, v[a], c[a]);
     }
     const double qi = q[i];
     int f = fstart[i];
+    if (!split) {   // one piece of weight 1 in cell c (as axis_pieces gives it)
+        const int leaf = c[0] + g.D * (c[1] + g.D * c[2]);
+        const int slot = leafstart[leaf] + atomicAdd(&cursor[leaf], 1);
+        const double s = g.s_leaf;
+        su[slot] = v[0] / s - c[0];
+        sv[slot] = v[1] / s - c[1];
+        sw[slot] = v[2] / s - c[2];
+        sq[slot] = R(qi);
+        spar[slot] = int(i);
+        sleaf[slot] = leaf;
+        gslot[f] = slot;
+        gw[f] = 1.0;
+        gdw[3 * int64_t(f) + 0] = 0.0;
+        gdw[3 * int64_t(f) + 1] = 0.0;
+        gdw[3 * int64_t(f) + 2] = 0.0;
+        return;
+    }
+    Pieces<N> P[3];
+    for (int a = 0; a < 3; ++a) axis_pieces<N, true>(g, seg, segden, v[a], P[a]);
     for (int kz = 0; kz < P[2].cnt; ++kz)
         for (int ky = 0; ky < P[1].cnt; ++ky)
             for (int kx = 0; kx < P[0].cnt; ++kx, ++f) {
@@ -668,19 +724,21 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
 
     // a1/a2: validate, split, count per cell, prefix sums
     int pk = prof_begin(plan, st);
-    EQ_CHECK(hipMemsetAsync(v.hdr, 0, sizeof(WsHeader), st));
-    EQ_CHECK(hipMemsetAsync(v.leafcnt, 0, 4 * (nleaf + 1), st));
-    EQ_CHECK(hipMemsetAsync(v.cursor, 0, 4 * nleaf, st));
-    k_count<N><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, n, pos, q, v.cnt, v.smask, v.leafcnt, v.hdr);
+    k_clear<<<blocks(nleaf + 1, 256), 256, 0, st>>>(v.hdr, v.leafcnt, v.cursor, nleaf);
+    k_count<N><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, n, pos, q, v.cnt, v.fstart, v.smask, v.leafcnt,
+                                                 v.hdr);
     EQ_CHECK(hipGetLastError());
-    int rc = scan(v.cnt, v.fstart, n, v.scanblk, st);
-    if (rc) return rc;
+    int rc = EQFMM_OK;
+    if (g.continuous) {   // fragments per charge vary only in the split modes
+        rc = scan(v.cnt, v.fstart, n, v.scanblk, st);
+        if (rc) return rc;
+    }
     rc = scan(v.leafcnt, v.leafstart, nleaf, v.scanblk, st);
     if (rc) return rc;
     WsHeader h;
-    int nfrag = 0;
+    int nfrag = int(n);   // one fragment per charge unless split
     EQ_CHECK(hipMemcpyAsync(&h, v.hdr, sizeof(WsHeader), hipMemcpyDeviceToHost, st));
-    EQ_CHECK(hipMemcpyAsync(&nfrag, v.fstart + n, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (g.continuous) EQ_CHECK(hipMemcpyAsync(&nfrag, v.fstart + n, sizeof(int), hipMemcpyDeviceToHost, st));
     EQ_CHECK(hipStreamSynchronize(st));
     if (h.flags & 2) return EQFMM_ENONFINITE;
     if (h.flags & 1) return EQFMM_EBOX;

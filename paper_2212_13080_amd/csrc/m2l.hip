@@ -372,6 +372,285 @@ __global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, co
     }
 }
 
+// ------------------------------------------------- LDS-staged float kernel
+
+// 16 bytes per lane from global memory straight into LDS: lane l's bytes land
+// at LDS byte address lds + 16 l (lds wave-uniform).  Written as inline
+// assembly so that the compiler neither inserts waits for these loads nor
+// moves LDS accesses across them; the kernel waits on vmcnt itself.
+__device__ __forceinline__ void lds_dma16(const void *gptr, uint32_t lds)
+{
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gptr), "s"(lds)
+                 : "memory", "m0");
+}
+
+// wait until at most V vector-memory operations of this wave are in flight
+template <int V> __device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(V >= 0 && V < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((V & 15) | ((V >> 4) << 14) | (7 << 4) | (15 << 8));
+    asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void wait_lgkm0()
+{
+    __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));
+    asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void wg_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Position of 16-byte piece c of lane q's row chunk among the CH pieces of
+// that lane in LDS: rotated so that the 64 lanes' reads of one piece index
+// fall on distinct banks (checked for 64 banks x 16 lanes and 32 banks x 8
+// lanes per pass).
+template <int CH> __device__ __forceinline__ int lds_rot(int q)
+{
+    if constexpr (CH == 1) return 0;
+    else if constexpr (CH == 2) return (q >> 2) + (q >> 3);
+    else if constexpr (CH == 4) return q + (q >> 2);
+    else return q + (q >> 3);
+}
+
+// Same contraction as k_m2l_mx, with the operands staged through LDS.
+//
+// A workgroup holds TPW = 4 / NSPLIT tiles of one (parity, node block) and
+// NSPLIT parts of the interaction list.  Per step every wave copies its
+// tile's chunk of source rows into LDS, 16 bytes per lane with consecutive
+// lanes on consecutive bytes of a row (coalesced), and the TPW waves of a
+// list part share one copy of the matrix chunk.  The copies go straight from
+// global memory to LDS into a ring of NST stages, NST - 1 steps ahead of the
+// products, so that reads that miss L2 are covered without holding them in
+// registers; one barrier per step publishes a stage and retires the oldest.
+template <int N, bool BF16, int CH, int NSPLIT, int NST>
+__global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, const int *__restrict__ mxtab,
+                                                 MxLevels lv, const float *__restrict__ phipad,
+                                                 float *__restrict__ loc_all, int nwg)
+{
+    using S = MxShape<N>;
+    constexpr int NS = S::NS, KH = S::KH, NB = S::NB;
+    constexpr int NA = KH / 4;            // 16-byte pieces of one half row
+    constexpr int NCH = NA / CH;          // steps per displacement
+    static_assert(NA % CH == 0 && (CH & (CH - 1)) == 0 && CH <= 8, "chunking");
+    static_assert(!BF16 || CH % 2 == 0, "bf16 steps take 8 sources per lane");
+    static_assert(NST >= 2, "ring depth");
+    using BT = typename std::conditional<BF16, bf16x8, float4>::type;
+    constexpr int NBL = BF16 ? CH / 2 : CH;   // matrix pieces per lane and step
+    constexpr int NBK = BF16 ? NA / 2 : NA;   // matrix pieces per lane, node block and displacement
+    constexpr int TPW = 4 / NSPLIT;
+    constexpr int BPW = (NBL + TPW - 1) / TPW;   // matrix copies per wave and step
+    constexpr int DPS = CH + BPW;                // copies per wave and step
+    constexpr int AU = 64 * CH, BU = 64 * NBL, SU = 4 * AU + NSPLIT * BU;   // 16-byte units
+    __shared__ float4 ring[NST * SU];
+    __shared__ int stab[kListLen];
+
+    const int per = gridDim.x >> 3;
+    int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (wg >= nwg) return;
+    int li = 0;
+    while (li + 1 < lv.nlev && wg >= lv.wg_begin[li + 1]) ++li;
+    wg -= lv.wg_begin[li];
+    const int level = lv.level[li], ntile = lv.ntile[li];
+    const float inv_side = lv.inv_side[li];
+    float *loc = loc_all + lv.cell0[li] * NS;
+    // workgroups (tile group, parity, node block), node block fastest
+    const int nb = wg % NB, tp = wg / NB;
+    const int p = tp & 7, tg = tp >> 3;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tw = wv % TPW, hs = wv / TPW;
+    const int t = tg * TPW + tw;
+    const bool active = t < ntile;
+    const int ta = active ? t : tg * TPW;   // idle waves copy a valid tile (and store nothing)
+    constexpr int OPS = kListLen / NSPLIT;
+    const int o_begin = hs * OPS, o_end = o_begin + OPS;
+    if (threadIdx.x < kListLen) stab[threadIdx.x] = mxtab[(level * 8 + p) * kListLen + threadIdx.x];
+    __syncthreads();
+
+    const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+    const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
+    const int64_t nparent = int64_t(Dp) * Dp * Dp;
+    const int64_t Pm0 = int64_t(ta) * 32;
+    const int x0 = 2 * compact3(Pm0) + px, y0 = 2 * compact3(Pm0 >> 1) + py, z0 = 2 * compact3(Pm0 >> 2) + pz;
+    const float *phi0 =
+        phipad + (lv.pcell0[li] + (int64_t(z0 + kHalo) * P + (y0 + kHalo)) * P + (x0 + kHalo)) * NS;
+    // source-row copies: copy m, lane l fills unit u = 64 m + l of the wave's
+    // chunk, i.e. piece c of consumer lane q = u / CH (cell q % 32, half q / 32)
+    uint32_t voffA[CH];
+#pragma unroll
+    for (int m = 0; m < CH; ++m) {
+        const int u = 64 * m + lane, q = u / CH;
+        const int c = ((u % CH) - lds_rot<CH>(q)) & (CH - 1);
+        const int64_t Pq = Pm0 + (q & 31);
+        const int64_t Pl = Pq < nparent ? Pq : Pm0;
+        const int cx = 2 * compact3(Pl) + px, cy = 2 * compact3(Pl >> 1) + py, cz = 2 * compact3(Pl >> 2) + pz;
+        voffA[m] = uint32_t((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + (q >> 5) * KH + 4 * c) * 4u;
+    }
+    // LDS addresses (bytes) of the ring, and this lane's read offsets
+    const uint32_t ring_lds = uint32_t(reinterpret_cast<uintptr_t>(ring));
+    const char *kb = static_cast<const char *>(Kmx) + size_t(nb) * NBK * 64 * sizeof(BT);
+
+    // the copies of one step: wave-uniform source bases and LDS destinations
+    struct Copy {
+        const char *ab, *bb;
+        uint32_t la, lb;
+    };
+    auto setup = [&](int step, auto bc) {
+        constexpr int b = decltype(bc)::value;
+        step = step < o_end * NCH ? step : o_end * NCH - 1;   // copies past the end land unused
+        const int oidx = step / NCH, ch = step - oidx * NCH;
+        const int e = __builtin_amdgcn_readfirstlane(stab[oidx]);
+        const int oi = e & 511, delta = e >> 9;
+        Copy cp;
+        cp.ab = reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS + ch * CH * 4);
+        cp.la = ring_lds + uint32_t((b * SU + wv * AU) * 16);
+        cp.bb = kb + (size_t(oi) * NB * NBK + size_t(ch) * NBL) * 64 * sizeof(BT);
+        cp.lb = ring_lds + uint32_t((b * SU + 4 * AU + hs * BU) * 16);
+        return cp;
+    };
+    auto copy_a = [&](const Copy &cp, int m) { lds_dma16(cp.ab + voffA[m], cp.la + m * 1024); };
+    auto copy_b = [&](const Copy &cp, int k) {
+        int j = tw + k * TPW;
+        j = j < NBL ? j : NBL - 1;   // surplus copies repeat the last piece
+        lds_dma16(cp.bb + (size_t(j) * 64 + lane) * sizeof(BT), cp.lb + j * 1024);
+    };
+    auto issue = [&](int step, auto bc) {
+        const Copy cp = setup(step, bc);
+#pragma unroll
+        for (int m = 0; m < CH; ++m) copy_a(cp, m);
+#pragma unroll
+        for (int k = 0; k < BPW; ++k) copy_b(cp, k);
+    };
+
+    float4 abuf[2][CH];
+    BT bbuf[2][NBL];
+    auto read = [&](auto bc, auto rc) {
+        constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
+        const float4 *ra = ring + b * SU + wv * AU + lane * CH;
+        const int rot = lds_rot<CH>(lane);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) abuf[r][c] = ra[(c + rot) & (CH - 1)];
+        const float4 *rb = ring + b * SU + 4 * AU + hs * BU + lane;
+#pragma unroll
+        for (int j = 0; j < NBL; ++j) {
+            const float4 v = rb[j * 64];
+            __builtin_memcpy(&bbuf[r][j], &v, 16);
+        }
+    };
+
+    floatx16 ca0 = {}, ca1 = {}, cb0 = {}, cb1 = {}, run = {};
+    // the products of 16-byte piece c (float) or pair of pieces (bf16) of
+    // register set r into (x0, x1)
+    auto product = [&](auto rc, int c, floatx16 &x0, floatx16 &x1) {
+        constexpr int r = decltype(rc)::value;
+        if constexpr (!BF16) {
+            const float4 a = abuf[r][c];
+            const float4 bv = bbuf[r][c];
+            x0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bv.x, x0, 0, 0, 0);
+            x1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bv.y, x1, 0, 0, 0);
+            x0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bv.z, x0, 0, 0, 0);
+            x1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bv.w, x1, 0, 0, 0);
+        } else {
+            const float4 a0 = abuf[r][2 * c], a1 = abuf[r][2 * c + 1];
+            bf16x8 a;
+            a[0] = __bf16(a0.x);
+            a[1] = __bf16(a0.y);
+            a[2] = __bf16(a0.z);
+            a[3] = __bf16(a0.w);
+            a[4] = __bf16(a1.x);
+            a[5] = __bf16(a1.y);
+            a[6] = __bf16(a1.z);
+            a[7] = __bf16(a1.w);
+            if (c & 1) x1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[r][c], x1, 0, 0, 0);
+            else x0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[r][c], x0, 0, 0, 0);
+        }
+    };
+    constexpr int NPR = BF16 ? NBL : CH;   // product groups per step
+
+    // Trip of TS steps: a multiple of NST (ring stage), of 2 (register set)
+    // and of 2 NCH (an even number of displacements, for the alternating
+    // accumulator pairs), unrolled so that all three are constants.
+    constexpr int TS = lcm_c(lcm_c(NST, 2), 2 * NCH), TD = TS / NCH;
+    static_assert(OPS % TD == 0, "pipeline trip");
+    const int s0 = o_begin * NCH;
+    static_for<0, NST>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        issue(s0 + j, std::integral_constant<int, j>{});
+    });
+    wait_vmcnt<(NST - 1) * DPS>();
+    wg_barrier();
+    read(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    for (int op = o_begin; op < o_end; op += TD) {
+        static_for<0, TS>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr int b = j % NST, r = j & 1, ch = j % NCH;
+            constexpr bool odd = (j / NCH) & 1;
+            const int s = op * NCH + j;
+            // this wave's copies of step s + 1 are done, and every wave has
+            // finished reading step s into registers
+            wait_vmcnt<(NST - 2) * DPS>();
+            wait_lgkm0();
+            wg_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            // step s + 1 into the other register set (its latency runs under
+            // this step's products)
+            read(std::integral_constant<int, (j + 1) % NST>{}, std::integral_constant<int, 1 - r>{});
+            const Copy cp = setup(s + NST, std::integral_constant<int, b>{});
+            floatx16 &x0 = odd ? cb0 : ca0, &x1 = odd ? cb1 : ca1;
+            if constexpr (ch == 0) x0 = x1 = floatx16{};
+            // products interleaved with the copies of step s + NST, in this
+            // order (the matrix cores run while the copies are issued)
+            static_for<0, NPR>([&](auto C) {
+                constexpr int c = decltype(C)::value;
+                product(std::integral_constant<int, r>{}, c, x0, x1);
+                if constexpr (c < CH) copy_a(cp, c);
+                __builtin_amdgcn_sched_barrier(0);
+            });
+            static_for<NPR, CH>([&](auto C) {
+                copy_a(cp, decltype(C)::value);
+            });
+            static_for<0, BPW>([&](auto K) { copy_b(cp, decltype(K)::value); });
+            if constexpr (ch == 0) {
+                if constexpr (odd) run += ca0 + ca1;
+                else run += cb0 + cb1;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+    run += cb0 + cb1;   // the last displacement (TD is even)
+    // no copy may still be writing LDS when the workgroup ends or reuses it
+    wait_vmcnt<0>();
+    wg_barrier();
+    if constexpr (NSPLIT > 1) {
+        floatx16 *red = reinterpret_cast<floatx16 *>(ring);   // [NSPLIT - 1][TPW][64]
+        if (hs > 0) red[((hs - 1) * TPW + tw) * 64 + lane] = run;
+        __syncthreads();
+        if (hs > 0) return;
+#pragma unroll
+        for (int h = 0; h < NSPLIT - 1; ++h) run += red[(h * TPW + tw) * 64 + lane];
+    }
+    if (!active) return;
+
+    // C[cell][node]: lane l, register r -> node j = l % 32, cell
+    // ii = 4 (l / 32) + (r % 4) + 8 (r / 4)
+    const int jn = nb * 32 + (lane & 31);
+    if (jn >= S::N3) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int ii = 4 * (lane >> 5) + (r & 3) + 8 * (r >> 2);
+        const int64_t P2 = Pm0 + ii;
+        if (P2 >= nparent) continue;
+        const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
+        const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
+        loc[c * NS + jn] = inv_side * run[r];
+    }
+}
+
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 // Double precision on the matrix cores (v_mfma_f64_16x16x4f64): a wave owns
@@ -530,10 +809,42 @@ template <int N> struct MxChunk {
     static constexpr int NST = N <= 4 ? 2 : 4;
 };
 
+// LDS-staged far field: 16-byte pieces per lane and step, ring depth
+template <int N> struct MxLds {
+    static constexpr int NA = MxShape<N>::KH / 4;
+    static constexpr int CH = NA % 4 == 0 ? 4 : 2;
+    static constexpr int NST = 3;
+};
+
+// Level table of the LDS-staged kernel: one workgroup per (group of tpw
+// tiles, parity, node block).
+int fill_levels_tg(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int nb, int tpw,
+                   MxLevels &lv)
+{
+    lv.nlev = lmax - lmin + 1;
+    int wgs = 0;
+    for (int i = 0; i < lv.nlev; ++i) {
+        const int l = lmin + i;
+        const int Dp = (1 << l) >> 1;
+        const int64_t nparent = int64_t(Dp) * Dp * Dp;
+        lv.level[i] = l;
+        lv.ntile[i] = int((nparent + 31) / 32);
+        lv.wg_begin[i] = wgs;
+        wgs += (lv.ntile[i] + tpw - 1) / tpw * 8 * nb;
+        lv.cell0[i] = lvl[l];
+        lv.pcell0[i] = plvl[l];
+        lv.inv_side[i] = float(double(1 << l) / g.box);
+        lv.inv_side64[i] = double(1 << l) / g.box;
+    }
+    lv.wg_begin[lv.nlev] = wgs;
+    return wgs;
+}
+
 template <int N>
 int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const float *phipad,
               float *loc, hipStream_t st)
 {
+    constexpr bool kLds = true;
     using S = MxShape<N>;
     constexpr int CH = MxChunk<N>::CH;
     const Geom &g = plan->g;
@@ -553,11 +864,16 @@ int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const in
     auto go = [&](int l0, int l1, bool use_bf) -> int {
         if (l0 > l1) return EQFMM_OK;
         MxLevels lv;
-        const int nwg = fill_levels(g, l0, l1, lvl, plvl, 32, S::NB, 4 / split, lv);
+        const int nwg = kLds ? fill_levels_tg(g, l0, l1, lvl, plvl, S::NB, 4 / split, lv)
+                             : fill_levels(g, l0, l1, lvl, plvl, 32, S::NB, 4 / split, lv);
         const int grid = (nwg + 7) & ~7;
         const void *K = use_bf ? Kbf : plan->ops.Kmx;
-#define EQ_M2L_LAUNCH(B, SP) \
-    k_m2l_mx<N, B, CH, SP, MxChunk<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg)
+#define EQ_M2L_LAUNCH(B, SP)                                                                            \
+    if (kLds)                                                                                           \
+        k_m2l_lds<N, B, MxLds<N>::CH, SP, MxLds<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, \
+                                                                              nwg);                    \
+    else                                                                                                \
+        k_m2l_mx<N, B, CH, SP, MxChunk<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg)
 #define EQ_M2L_SPLIT(B)                          \
     if (split == 1) EQ_M2L_LAUNCH(B, 1);         \
     else if (split == 2) EQ_M2L_LAUNCH(B, 2);    \
