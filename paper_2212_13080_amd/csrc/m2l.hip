@@ -375,14 +375,20 @@ __global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, co
 // ------------------------------------------------- LDS-staged float kernel
 
 // 16 bytes per lane from global memory straight into LDS: lane l's bytes land
-// at LDS byte address lds + 16 l (lds wave-uniform).  Written as inline
-// assembly so that the compiler neither inserts waits for these loads nor
-// moves LDS accesses across them; the kernel waits on vmcnt itself.
+// at LDS byte address lds + 16 l (lds wave-uniform, passed in M0).  Written
+// as inline assembly because the compiler, for its own LDS-DMA builtin,
+// waits for every copy in flight before any LDS read, which would undo the
+// ring; here the kernel waits on vmcnt itself.  M0 is a reserved register:
+// the far-field kernels hold no value of their own in it (every M0 write in
+// their code comes from this block), so overwriting it is safe.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
 __device__ __forceinline__ void lds_dma16(const void *gptr, uint32_t lds)
 {
     asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gptr), "s"(lds)
                  : "memory", "m0");
 }
+#pragma clang diagnostic pop
 
 // wait until at most V vector-memory operations of this wave are in flight
 template <int V> __device__ __forceinline__ void wait_vmcnt()
