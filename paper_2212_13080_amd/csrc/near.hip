@@ -107,27 +107,33 @@ __device__ __forceinline__ void p2p_term(C ex, C ey, C ez, C q, bool self, C &ph
     f2 += qr3 * ez;
 }
 
-// sources [jl, jh) of the staged chunk; displacement formed in double from
-// the cell-local coordinates and the cell offset (ex = target - source)
-template <typename C, typename R>
-__device__ __forceinline__ void p2p_range(const double *lu, const double *lv, const double *lw, const R *lq,
-                                          const int *lpar, const int *ldx, int jl, int jh, int S, double ud,
-                                          double vy, double wz, int tx, int par, double sd, C &ph, C &f0,
-                                          C &f1, C &f2)
+// Staged sources [jl, jh), every S-th.  The displacement (target - source)
+// is formed in double from cell-local coordinates: ex from xt - lx[j], where
+// xt = target x + target cell and lx[j] = source x + its unwrapped cell (or,
+// with UNWRAP false, from ud + (tx - ldx[j]) - lx[j] with lx the bare
+// source x); self and same-charge pairs are recognised by the staged index
+// oself (SELF_BY_INDEX, one fragment per charge) or by the owner.
+template <typename C, typename R, bool UNWRAP, bool SELF_BY_INDEX>
+__device__ __forceinline__ void p2p_range(const double *lx, const double *lv, const double *lw, const R *lq,
+                                          const int *lpar, const int *ldx, int jl, int jh, int S, double xt,
+                                          double ud, int tx, double vy, double wz, int par, int oself, double sd,
+                                          C &ph, C &f0, C &f1, C &f2)
 {
 #pragma unroll 2
     for (int j = jl; j < jh; j += S) {
-        const C ex = C((ud + double(tx - ldx[j]) - lu[j]) * sd);
+        const double dx = UNWRAP ? xt - lx[j] : ud + double(tx - ldx[j]) - lx[j];
+        const C ex = C(dx * sd);
         const C ey = C((vy - lv[j]) * sd);
         const C ez = C((wz - lw[j]) * sd);
-        p2p_term<C>(ex, ey, ez, C(lq[j]), lpar[j] == par, ph, f0, f1, f2);
+        const bool self = SELF_BY_INDEX ? j == oself : lpar[j] == par;
+        p2p_term<C>(ex, ey, ez, C(lq[j]), self, ph, f0, f1, f2);
     }
 }
 
 // One segment of source cells in a neighbouring row: cells [lo, hi) of row
 // base rb, whose unwrapped x index is the cell index + shift.
 struct Seg {
-    int rb, lo, hi, shift, dy, dz;
+    int rb, lo, hi, shift, dy, dz, r;
 };
 
 // the up to 27 segments (9 rows x main / left wrap / right wrap) of the
@@ -146,9 +152,10 @@ __device__ __forceinline__ int row_segments(const Geom &g, int y, int z, int c0,
                 continue;
             }
             const int rb = (yy + D * zz) * D;
-            out[m++] = Seg{rb, c0 - 1 > 0 ? c0 - 1 : 0, c1 + 1 < D ? c1 + 1 : D, 0, dy, dz};
-            if (g.periodic && c0 == 0) out[m++] = Seg{rb, D - 1, D, -D, dy, dz};
-            if (g.periodic && c1 == D) out[m++] = Seg{rb, 0, 1, D, dy, dz};
+            const int r = 3 * (dz + 1) + (dy + 1);
+            out[m++] = Seg{rb, c0 - 1 > 0 ? c0 - 1 : 0, c1 + 1 < D ? c1 + 1 : D, 0, dy, dz, r};
+            if (g.periodic && c0 == 0) out[m++] = Seg{rb, D - 1, D, -D, dy, dz, r};
+            if (g.periodic && c1 == D) out[m++] = Seg{rb, 0, 1, D, dy, dz, r};
         }
     return m;
 }
@@ -174,15 +181,18 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
                                               const R *locL, double *sphi, R *sfld)
 {
     using O = NearShape<N>;
-    __shared__ double lu[kChunk], lv[kChunk], lw[kChunk];
+    // float modes stage the unwrapped source x (cell + x) and so need no
+    // per-source cell; double mode keeps the two apart (exact differences)
+    constexpr bool UNWRAP = sizeof(R) == sizeof(float);
+    __shared__ double lx[kChunk], lv[kChunk], lw[kChunk];
     __shared__ R lq[kChunk];
-    __shared__ int lpar[kChunk], ldx[kChunk];
+    __shared__ int lpar[kChunk], ldx[UNWRAP ? 1 : kChunk];
     __shared__ double red[3 * 4 * 64];   // slices 1..S-1, four sums, TT targets
-    // segment 3r + kind of neighbour row r = 3 (dz + 1) + (dy + 1): kind 0 is
-    // the cells c0-1 .. c1 of that row, kinds 1 and 2 the periodic images of
-    // cells D-1 and 0 beyond the walls; unused segments are empty (lo == hi)
+    // the non-empty segments among 3r + kind of neighbour row r = 3 (dz + 1)
+    // + (dy + 1): kind 0 is the cells c0-1 .. c1 of that row, kinds 1 and 2
+    // the periodic images of cells D-1 and 0 beyond the walls
     __shared__ Seg segs[27];
-    __shared__ int sbase[28], sj0[27];
+    __shared__ int sbase[28], sj0[27], nseg_s;
     __shared__ int rls[9][kMaxRB + 3];   // leafstart of cells c0-1 .. c1+1 (clamped to [0, D]) of each row
     const int D = g.D;
     const int nxb = (D + RB - 1) / RB;
@@ -215,14 +225,15 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
         c = c < 0 ? 0 : (c > D ? D : c);
         rls[r][i] = ok ? leafstart[rb + c] : 0;
     }
-    if (threadIdx.x < 64) {   // wave 0: segments and their exclusive prefix
+    if (threadIdx.x < 64) {   // wave 0: the non-empty segments, compacted, and their prefix
         const int k = threadIdx.x;
-        int cnt = 0;
+        int cnt = 0, j0 = 0;
+        Seg sg{0, 0, 0, 0, 0, 0, 0};
         if (k < 27) {
             const int r = k / 3, kind = k - 3 * r;
             bool ok;
             const int rb = row_base(r, ok);
-            Seg sg{rb, 0, 0, 0, r % 3 - 1, r / 3 - 1};
+            sg = Seg{rb, 0, 0, 0, r % 3 - 1, r / 3 - 1, r};
             if (ok) {
                 if (kind == 0) {
                     sg.lo = c0 - 1 > 0 ? c0 - 1 : 0;
@@ -237,25 +248,32 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
                     sg.shift = D;
                 }
             }
-            int j0 = 0;
             if (sg.hi > sg.lo) {
                 j0 = leafstart[rb + sg.lo];
                 cnt = leafstart[rb + sg.hi] - j0;
             }
-            segs[k] = sg;
-            sj0[k] = j0;
         }
+        const bool live = sg.hi > sg.lo;
+        const uint64_t mask = __ballot(live);
+        const int pos = __popcll(mask & ((uint64_t(1) << k) - 1));
         int incl = cnt;
 #pragma unroll
         for (int off = 1; off < 32; off <<= 1) {
             const int v = __shfl_up(incl, off, 64);
             if (k >= off) incl += v;
         }
-        if (k < 27) sbase[k] = incl - cnt;
-        if (k == 26) sbase[27] = incl;
+        if (live) {
+            segs[pos] = sg;
+            sj0[pos] = j0;
+            sbase[pos] = incl - cnt;
+        }
+        if (k == 26) {
+            nseg_s = __popcll(mask);
+            sbase[__popcll(mask)] = incl;
+        }
     }
     __syncthreads();
-    const int nsrc = sbase[27];
+    const int nseg = nseg_s, nsrc = sbase[nseg];
     // Sparse blocks stage every source once in LDS and split each target over
     // S threads; dense neighbourhoods are read from global memory.
     const bool staged = nsrc <= kChunk;
@@ -271,14 +289,19 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
             int k = 0;
 #pragma unroll
             for (int step = 16; step > 0; step >>= 1)
-                if (k + step < 27 && sbase[k + step] <= o) k += step;
+                if (k + step < nseg && sbase[k + step] <= o) k += step;
             const int j = sj0[k] + (o - sbase[k]);
-            lu[o] = su[j];
+            const int dxc = (sleaf[j] & (D - 1)) + segs[k].shift;
+            if constexpr (UNWRAP) {
+                lx[o] = double(dxc) + su[j];
+            } else {
+                lx[o] = su[j];
+                ldx[o] = dxc;
+            }
             lv[o] = sv[j];
             lw[o] = sw[j];
             lq[o] = sq[j];
             lpar[o] = spar[j];
-            ldx[o] = (sleaf[j] & (D - 1)) + segs[k].shift;
         }
         __syncthreads();
     }
@@ -290,6 +313,7 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
         const int par = spar[tt];
         const int leaf = sleaf[tt];
         const int tx = leaf & (D - 1);
+        const double xt = ud + double(tx);
         const bool dbl = mixed && smask[par];
         R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
         double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
@@ -297,17 +321,16 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
         if (act) {
             if (dbl) l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, sl, S, dph, df0, df1, df2);
             else l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), sl, S, ph, f0, f1, f2);
-            for (int k = 0; k < 27; ++k) {
+            for (int k = 0; k < nseg; ++k) {
                 const Seg sg = segs[k];
-                if (sg.hi == sg.lo) continue;
                 // sources of cells tx-1 .. tx+1 in this segment, as global indices
                 int j0, j1;
                 if (sg.shift == 0) {
                     const int a = tx - 1 > sg.lo ? tx - 1 : sg.lo;
                     const int b = tx + 1 < sg.hi - 1 ? tx + 1 : sg.hi - 1;
                     if (a > b) continue;
-                    j0 = rls[k / 3][a - (c0 - 1)];
-                    j1 = rls[k / 3][b + 1 - (c0 - 1)];
+                    j0 = rls[sg.r][a - (c0 - 1)];
+                    j1 = rls[sg.r][b + 1 - (c0 - 1)];
                 } else {
                     // an image cell beyond a wall neighbours only the cell at that wall
                     if (sg.shift < 0 ? tx != 0 : tx != D - 1) continue;
@@ -317,12 +340,17 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
                 const double vy = vd - sg.dy, wz = wd - sg.dz;
                 if (staged) {
                     const int off = sbase[k] - sj0[k];
+                    // one fragment per charge: the self pair is the target's own slot
+                    const int oself = t + off;
                     if (dbl)
-                        p2p_range<double, R>(lu, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, ud, vy, wz, tx,
-                                             par, sd, dph, df0, df1, df2);
+                        p2p_range<double, R, UNWRAP, false>(lx, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S,
+                                                            xt, ud, tx, vy, wz, par, oself, sd, dph, df0, df1, df2);
+                    else if (g.continuous)
+                        p2p_range<R, R, UNWRAP, false>(lx, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, xt,
+                                                       ud, tx, vy, wz, par, oself, sd, ph, f0, f1, f2);
                     else
-                        p2p_range<R, R>(lu, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, ud, vy, wz, tx, par,
-                                        sd, ph, f0, f1, f2);
+                        p2p_range<R, R, UNWRAP, true>(lx, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, xt,
+                                                      ud, tx, vy, wz, par, oself, sd, ph, f0, f1, f2);
                 } else {
                     for (int j = j0; j < j1; ++j) {
                         const double ex = ud + double(tx - ((sleaf[j] & (D - 1)) + sg.shift)) - su[j];
