@@ -26,8 +26,10 @@
  * workspace, inputs, outputs).  The library never allocates device memory;
  * it owns only the host-side plan object.  All device pointers are HIP
  * device addresses on the current device; `stream` is a hipStream_t (NULL =
- * default stream).  Work is enqueued on that stream; eqfmm_forward blocks
- * once per call to read back an 8-byte status (fragment count, error bits).
+ * default stream).  Work is enqueued on that stream (eqfmm_forward also uses
+ * the plan's own stream, joined back into the caller's before the final
+ * kernels); eqfmm_forward blocks once per call to read back an 8-byte status
+ * (fragment count, error bits).
  *
  * Error behaviour: every call returns EQFMM_OK (0) or a negative code.
  * Data-dependent errors (EBOX, ENEUTRAL, ENONFINITE, fragment capacity) are
@@ -66,7 +68,8 @@ enum {
     EQFMM_ENONFINITE = -4,  /* a position or charge is NaN or infinite              */
     EQFMM_EWORKSPACE = -5,  /* workspace too small or fragment capacity exceeded    */
     EQFMM_EHIP = -6,        /* a HIP runtime call failed                            */
-    EQFMM_ESTATE = -7       /* backward without a matching forward on this workspace */
+    EQFMM_ESTATE = -7       /* backward without a matching forward on this workspace,
+                               or forward before eqfmm_plan_upload                    */
 };
 
 typedef struct {
@@ -96,7 +99,10 @@ int eqfmm_plan_device_bytes(const eqfmm_plan *plan, size_t *bytes);
 
 /* Copy the plan's operators into the caller's device buffer (rounded to the
  * working precision).  Synchronises `stream`.  The buffer must outlive every
- * later call with this plan. */
+ * later call with this plan.  The first upload also creates, on the current
+ * device, the plan's own non-blocking stream (default priority) and two
+ * events: eqfmm_forward runs the near field there, concurrently with the far
+ * field, and joins it back into the caller's stream before it returns. */
 int eqfmm_plan_upload(eqfmm_plan *plan, void *dev_buf, size_t bytes, void *stream);
 
 /* Bytes of workspace needed for n charges (an upper bound that includes the

@@ -65,7 +65,7 @@ struct WsLayout {
     size_t hdr, cnt, fstart, smask, leafcnt, leafstart, cursor, scanblk;
     size_t su, sv, sw, sq, spar, sleaf;
     size_t gslot, gw, gdw;
-    size_t phi, phipad, loc, sphi, sfld, epart;
+    size_t phi, phipad, loc, sphi, snf, sfld, epart;
     size_t total;
     int64_t scan_blocks, e_blocks;
     std::vector<int64_t> lvl;     // first cell of each level in the Phi / L arrays
@@ -94,6 +94,10 @@ struct eqfmm_plan {
     const void *last_ws = nullptr;
     int64_t last_n = -1, last_nfrag = 0;
     eqfmm::Profile prof;
+    // the near field runs on a stream of its own, concurrent with the far
+    // field; created with the plan's upload on the device in use then
+    hipStream_t side = nullptr;
+    hipEvent_t ev_bin = nullptr, ev_near = nullptr;
 };
 
 namespace eqfmm {

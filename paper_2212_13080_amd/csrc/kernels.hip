@@ -656,7 +656,7 @@ template <typename R> struct Ws {
     int *cnt, *fstart, *leafcnt, *leafstart, *cursor, *scanblk, *spar, *sleaf, *gslot;
     unsigned char *smask;
     R *sq, *phi, *phipad, *loc, *sfld;
-    double *su, *sv, *sw, *gw, *gdw, *sphi, *epart;
+    double *su, *sv, *sw, *gw, *gdw, *sphi, *snf, *epart;
 };
 
 template <typename R> Ws<R> views(unsigned char *b, const WsLayout &W)
@@ -683,6 +683,7 @@ template <typename R> Ws<R> views(unsigned char *b, const WsLayout &W)
     v.phipad = reinterpret_cast<R *>(b + W.phipad);
     v.loc = reinterpret_cast<R *>(b + W.loc);
     v.sphi = reinterpret_cast<double *>(b + W.sphi);
+    v.snf = reinterpret_cast<double *>(b + W.snf);
     v.sfld = reinterpret_cast<R *>(b + W.sfld);
     v.epart = reinterpret_cast<double *>(b + W.epart);
     return v;
@@ -692,12 +693,15 @@ unsigned blocks(int64_t work, int per) { return unsigned((work + per - 1) / per)
 
 }  // namespace
 
-// far field at the charges and near field (near.hip)
+// near field, and far field at the charges (near.hip)
+template <typename R>
+int launch_p2p(const eqfmm_plan *plan, int64_t nfrag, const int *leafstart, const double *su, const double *sv,
+               const double *sw, const R *sq, const int *spar, const int *sleaf, const unsigned char *smask,
+               double *sphi, double *snf, hipStream_t st);
 template <int N, typename R>
-int launch_near(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const int *leafstart,
-                const double *su, const double *sv, const double *sw, const R *sq, const int *spar,
-                const int *sleaf, const unsigned char *smask, const R *locL, double *sphi, R *sfld,
-                hipStream_t st);
+int launch_l2p(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const double *su, const double *sv,
+               const double *sw, const int *spar, const int *sleaf, const unsigned char *smask, const R *locL,
+               double *sphi, const double *snf, R *sfld, hipStream_t st);
 
 // far field (declared here, defined with the matrix-core kernels in m2l.hip):
 // the haloed copy of Phi at levels lmin..lmax, then the products of every
@@ -751,6 +755,18 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     EQ_CHECK(hipGetLastError());
     prof_end(plan, st, pk, EQFMM_STAGE_BIN, 0.0, double(n) * 64.0 + double(nfrag) * 40.0);
 
+    // a8: near field on the side stream, concurrent with a3-a6
+    hipStream_t sd = plan->side;
+    if (!sd) return EQFMM_ESTATE;
+    EQ_CHECK(hipEventRecord(plan->ev_bin, st));
+    EQ_CHECK(hipStreamWaitEvent(sd, plan->ev_bin, 0));
+    pk = prof_begin(plan, sd);
+    rc = launch_p2p<R>(plan, nfrag, v.leafstart, v.su, v.sv, v.sw, v.sq, v.spar, v.sleaf, v.smask, v.sphi, v.snf,
+                       sd);
+    if (rc) return rc;
+    prof_end(plan, sd, pk, EQFMM_STAGE_LEAF, 0.0, 0.0);
+    EQ_CHECK(hipEventRecord(plan->ev_near, sd));
+
     // a3: replacement at the finest cells
     const int L = g.L;
     pk = prof_begin(plan, st);
@@ -799,10 +815,11 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
         prof_end(plan, st, pk, EQFMM_STAGE_L2L, 0.0, 0.0);
     }
 
-    // a7/a8: far field at the fragments and the near field
+    // a7: far field at the fragments, added to the near-field sums
+    EQ_CHECK(hipStreamWaitEvent(st, plan->ev_near, 0));
     pk = prof_begin(plan, st);
-    rc = launch_near<N, R>(plan, nfrag, t, den, v.leafstart, v.su, v.sv, v.sw, v.sq, v.spar, v.sleaf, v.smask,
-                           v.loc + W.lvl[L] * O::NS, v.sphi, v.sfld, st);
+    rc = launch_l2p<N, R>(plan, nfrag, t, den, v.su, v.sv, v.sw, v.spar, v.sleaf, v.smask, v.loc + W.lvl[L] * O::NS,
+                          v.sphi, v.snf, v.sfld, st);
     if (rc) return rc;
     prof_end(plan, st, pk, EQFMM_STAGE_LEAF, 0.0, 0.0);
 

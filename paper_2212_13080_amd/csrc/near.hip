@@ -1,21 +1,25 @@
-// Far field at the charges (a7) and near field (a8): for every fragment,
-// Psi of its finest cell evaluated on the replacement of a unit charge there
-// (Sec. 2.2 step 4 and the force rule after step 5), plus the direct sum over
-// the same and the 26 adjacent finest cells (Sec. 1, Sec. 2.2 step 5);
-// fragments of the same charge do not interact.
+// Near field (a8) and far field at the charges (a7).  For every fragment:
+// the direct sum over the same and the 26 adjacent finest cells (Sec. 1,
+// Sec. 2.2 step 5), fragments of the same charge excluded; then Psi of its
+// finest cell evaluated on the replacement of a unit charge there (Sec. 2.2
+// step 4 and the force rule after step 5), added in a second kernel.  The
+// direct sum needs only the binned charges, so it runs concurrently with the
+// upward pass and the far field; the second kernel waits for the local
+// vectors.
 //
-// Work decomposition: fragments are sorted by finest cell in row-major order
-// (x fastest), so the cells x-1..x+1 of one row (y, z) are one contiguous
-// range.  A workgroup owns RB consecutive cells of one x-row (about 64
-// targets).  When its 9 neighbouring rows hold at most kChunk sources, it
-// stages them all in LDS at once and each target reads the sub-ranges of its
-// own three cells per row, with S = 2 or 4 threads per target taking every
-// S-th source (their sums are added in a fixed order at the end).  Dense
-// blocks (clustered charges) read the same windows from global memory
-// instead: the lanes of a wave then mostly share a cell and the loads are
-// broadcasts.  Targets whose charge is split are evaluated in
+// Work decomposition of the direct sum: fragments are sorted by finest cell
+// in row-major order (x fastest), so the cells x-1..x+1 of one row (y, z)
+// are one contiguous range.  A workgroup owns RB consecutive cells of one
+// x-row (about 64 targets).  When its 9 neighbouring rows hold at most
+// kChunk sources, it stages them all in LDS at once and each target reads
+// the sub-ranges of its own three cells per row, with S = 2 or 4 threads per
+// target taking every S-th source (their sums are added in a fixed order at
+// the end).  Dense blocks (clustered charges) read the same windows from
+// global memory instead: the lanes of a wave then mostly share a cell and
+// the loads are broadcasts.  Targets whose charge is split are evaluated in
 // double even in the float modes (the force along a split axis is a short
-// sum of large cancelling terms).
+// sum of large cancelling terms).  Near-field sums are kept in double until
+// the far field is added.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -174,13 +178,12 @@ __device__ __forceinline__ void window(const int *leafstart, const Seg &sg, int 
     j1 = leafstart[sg.rb + b + 1];
 }
 
-template <int N, typename R>
-__global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_, int RB, const int *leafstart,
-                                              const double *su, const double *sv, const double *sw, const R *sq,
-                                              const int *spar, const int *sleaf, const unsigned char *smask,
-                                              const R *locL, double *sphi, R *sfld)
+template <typename R>
+__global__ void __launch_bounds__(256) k_near(Geom g, int RB, const int *leafstart, const double *su,
+                                              const double *sv, const double *sw, const R *sq, const int *spar,
+                                              const int *sleaf, const unsigned char *smask, double *sphi,
+                                              double *snf)
 {
-    using O = NearShape<N>;
     // float modes stage the unwrapped source x (cell + x) and so need no
     // per-source cell; double mode keeps the two apart (exact differences)
     constexpr bool UNWRAP = sizeof(R) == sizeof(float);
@@ -317,10 +320,7 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
         const bool dbl = mixed && smask[par];
         R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
         double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
-        const R *Lc = locL + int64_t(leaf) * O::NS;
         if (act) {
-            if (dbl) l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, sl, S, dph, df0, df1, df2);
-            else l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), sl, S, ph, f0, f1, f2);
             for (int k = 0; k < nseg; ++k) {
                 const Seg sg = segs[k];
                 // sources of cells tx-1 .. tx+1 in this segment, as global indices
@@ -386,9 +386,9 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
         }
         if (act && sl == 0) {
             sphi[t] = o0;
-            sfld[3 * int64_t(t) + 0] = R(o1);
-            sfld[3 * int64_t(t) + 1] = R(o2);
-            sfld[3 * int64_t(t) + 2] = R(o3);
+            snf[3 * int64_t(t) + 0] = o1;
+            snf[3 * int64_t(t) + 1] = o2;
+            snf[3 * int64_t(t) + 2] = o3;
         }
     }
 }
@@ -397,14 +397,12 @@ __global__ void __launch_bounds__(256) k_near(Geom g, const R *t_, const R *den_
 // Targets of dense row blocks (>= kDense targets), one thread each over the
 // sorted fragments: the lanes of a wave then mostly share a cell, so every
 // source load is a broadcast, and a large cluster spreads over many waves.
-template <int N, typename R>
-__global__ void __launch_bounds__(256) k_near_dense(Geom g, const R *t_, const R *den_, int RB, int64_t nfrag,
-                                                    const int *leafstart, const double *su, const double *sv,
-                                                    const double *sw, const R *sq, const int *spar,
-                                                    const int *sleaf, const unsigned char *smask, const R *locL,
-                                                    double *sphi, R *sfld)
+template <typename R>
+__global__ void __launch_bounds__(256) k_near_dense(Geom g, int RB, int64_t nfrag, const int *leafstart,
+                                                    const double *su, const double *sv, const double *sw,
+                                                    const R *sq, const int *spar, const int *sleaf,
+                                                    const unsigned char *smask, double *sphi, double *snf)
 {
-    using O = NearShape<N>;
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= nfrag) return;
     const int D = g.D;
@@ -416,11 +414,8 @@ __global__ void __launch_bounds__(256) k_near_dense(Geom g, const R *t_, const R
     const double ud = su[t], vd = sv[t], wd = sw[t];
     const int par = spar[t];
     const bool dbl = sizeof(R) == sizeof(float) && g.continuous && smask[par];
-    const R *Lc = locL + int64_t(leaf) * O::NS;
     R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
     double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
-    if (dbl) l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, 0, 1, dph, df0, df1, df2);
-    else l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), 0, 1, ph, f0, f1, f2);
     Seg segs[27];
     const int nseg = row_segments(g, y, z, tx, tx + 1, segs);
     for (int k = 0; k < nseg; ++k) {
@@ -437,19 +432,50 @@ __global__ void __launch_bounds__(256) k_near_dense(Geom g, const R *t_, const R
         }
     }
     sphi[t] = dbl ? dph : double(ph);
-    sfld[3 * t + 0] = R(dbl ? df0 : double(f0));
-    sfld[3 * t + 1] = R(dbl ? df1 : double(f1));
-    sfld[3 * t + 2] = R(dbl ? df2 : double(f2));
+    snf[3 * t + 0] = dbl ? df0 : double(f0);
+    snf[3 * t + 1] = dbl ? df1 : double(f1);
+    snf[3 * t + 2] = dbl ? df2 : double(f2);
+}
+
+// Far field at the fragments (a7), added to their near-field sums: Psi of
+// the fragment's finest cell evaluated on the replacement of a unit charge
+// there, and its gradient.
+template <int N, typename R>
+__global__ void __launch_bounds__(256) k_l2p(Geom g, const R *t_, const R *den_, int64_t nfrag, const double *su,
+                                             const double *sv, const double *sw, const int *spar,
+                                             const int *sleaf, const unsigned char *smask, const R *locL,
+                                             double *sphi, const double *snf, R *sfld)
+{
+    using O = NearShape<N>;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= nfrag) return;
+    const double sd = g.s_leaf;
+    const double ud = su[t], vd = sv[t], wd = sw[t];
+    const bool dbl = sizeof(R) == sizeof(float) && g.continuous && smask[spar[t]];
+    const R *Lc = locL + int64_t(sleaf[t]) * O::NS;
+    double a0, a1, a2, a3;
+    if (dbl) {
+        double ph = 0.0, f0 = 0.0, f1 = 0.0, f2 = 0.0;
+        l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, 0, 1, ph, f0, f1, f2);
+        a0 = ph, a1 = f0, a2 = f1, a3 = f2;
+    } else {
+        R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
+        l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), 0, 1, ph, f0, f1, f2);
+        a0 = ph, a1 = f0, a2 = f1, a3 = f2;
+    }
+    sphi[t] += a0;
+    sfld[3 * t + 0] = R(snf[3 * t + 0] + a1);
+    sfld[3 * t + 1] = R(snf[3 * t + 1] + a2);
+    sfld[3 * t + 2] = R(snf[3 * t + 2] + a3);
 }
 
 }  // namespace
 
 // cells per workgroup row block: about 64 targets on average
-template <int N, typename R>
-int launch_near(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const int *leafstart,
-                const double *su, const double *sv, const double *sw, const R *sq, const int *spar,
-                const int *sleaf, const unsigned char *smask, const R *locL, double *sphi, R *sfld,
-                hipStream_t st)
+template <typename R>
+int launch_p2p(const eqfmm_plan *plan, int64_t nfrag, const int *leafstart, const double *su, const double *sv,
+               const double *sw, const R *sq, const int *spar, const int *sleaf, const unsigned char *smask,
+               double *sphi, double *snf, hipStream_t st)
 {
     const Geom &g = plan->g;
     const double mean = double(nfrag) / (double(g.D) * g.D * g.D);
@@ -458,23 +484,40 @@ int launch_near(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den,
     RB = RB > kMaxRB ? kMaxRB : RB;
     const int nxb = (g.D + RB - 1) / RB;
     const int64_t grid = int64_t(g.D) * g.D * nxb;
-    k_near<N, R><<<dim3(unsigned(grid)), 256, 0, st>>>(g, t, den, RB, leafstart, su, sv, sw, sq, spar, sleaf,
-                                                       smask, locL, sphi, sfld);
+    k_near<R><<<dim3(unsigned(grid)), 256, 0, st>>>(g, RB, leafstart, su, sv, sw, sq, spar, sleaf, smask, sphi,
+                                                    snf);
     if (nfrag > 0)
-        k_near_dense<N, R><<<dim3(unsigned((nfrag + 255) / 256)), 256, 0, st>>>(
-            g, t, den, RB, nfrag, leafstart, su, sv, sw, sq, spar, sleaf, smask, locL, sphi, sfld);
+        k_near_dense<R><<<dim3(unsigned((nfrag + 255) / 256)), 256, 0, st>>>(g, RB, nfrag, leafstart, su, sv, sw,
+                                                                            sq, spar, sleaf, smask, sphi, snf);
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
 
-#define EQ_NEAR_INST(NN, RR)                                                                              \
-    template int launch_near<NN, RR>(const eqfmm_plan *, int64_t, const RR *, const RR *, const int *,    \
-                                     const double *, const double *, const double *, const RR *,        \
-                                     const int *, const int *, const unsigned char *, const RR *,       \
-                                     double *, RR *, hipStream_t);
-EQ_NEAR_INST(2, float) EQ_NEAR_INST(3, float) EQ_NEAR_INST(4, float) EQ_NEAR_INST(5, float)
-EQ_NEAR_INST(6, float) EQ_NEAR_INST(7, float)
-EQ_NEAR_INST(2, double) EQ_NEAR_INST(3, double) EQ_NEAR_INST(4, double) EQ_NEAR_INST(5, double)
-EQ_NEAR_INST(6, double) EQ_NEAR_INST(7, double)
-#undef EQ_NEAR_INST
+template <int N, typename R>
+int launch_l2p(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const double *su, const double *sv,
+               const double *sw, const int *spar, const int *sleaf, const unsigned char *smask, const R *locL,
+               double *sphi, const double *snf, R *sfld, hipStream_t st)
+{
+    if (nfrag > 0)
+        k_l2p<N, R><<<dim3(unsigned((nfrag + 255) / 256)), 256, 0, st>>>(plan->g, t, den, nfrag, su, sv, sw, spar,
+                                                                         sleaf, smask, locL, sphi, snf, sfld);
+    return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+}
+
+template int launch_p2p<float>(const eqfmm_plan *, int64_t, const int *, const double *, const double *,
+                               const double *, const float *, const int *, const int *, const unsigned char *,
+                               double *, double *, hipStream_t);
+template int launch_p2p<double>(const eqfmm_plan *, int64_t, const int *, const double *, const double *,
+                                const double *, const double *, const int *, const int *, const unsigned char *,
+                                double *, double *, hipStream_t);
+#define EQ_L2P_INST(NN, RR)                                                                                  \
+    template int launch_l2p<NN, RR>(const eqfmm_plan *, int64_t, const RR *, const RR *, const double *,      \
+                                    const double *, const double *, const int *, const int *,               \
+                                    const unsigned char *, const RR *, double *, const double *, RR *,      \
+                                    hipStream_t);
+EQ_L2P_INST(2, float) EQ_L2P_INST(3, float) EQ_L2P_INST(4, float) EQ_L2P_INST(5, float)
+EQ_L2P_INST(6, float) EQ_L2P_INST(7, float)
+EQ_L2P_INST(2, double) EQ_L2P_INST(3, double) EQ_L2P_INST(4, double) EQ_L2P_INST(5, double)
+EQ_L2P_INST(6, double) EQ_L2P_INST(7, double)
+#undef EQ_L2P_INST
 
 }  // namespace eqfmm

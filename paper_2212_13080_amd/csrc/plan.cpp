@@ -278,6 +278,7 @@ WsLayout ws_layout(const eqfmm_plan *plan, int64_t n)
     W.phipad = take(rs * pcells * g.ns);
     W.loc = take(rs * ncells * g.ns);
     W.sphi = take(sizeof(double) * W.fcap);
+    W.snf = take(sizeof(double) * 3 * W.fcap);   // near-field sums before the far field is added
     W.sfld = take(rs * 3 * W.fcap);
     W.epart = take(sizeof(double) * W.e_blocks);
     W.total = off;
@@ -369,6 +370,13 @@ int eqfmm_plan_upload(eqfmm_plan *plan, void *dev_buf, size_t bytes, void *strea
     plan->ops.T = b + plan->off_T;
     plan->ops.Kmx = b + plan->off_Kmx;
     plan->ops.mxtab = reinterpret_cast<const int *>(b + plan->off_mxtab);
+    if (!plan->side) {
+        // default priority; non-blocking so that it never waits on the legacy stream by itself
+        if (hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking) != hipSuccess) return EQFMM_EHIP;
+        if (hipEventCreateWithFlags(&plan->ev_bin, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&plan->ev_near, hipEventDisableTiming) != hipSuccess)
+            return EQFMM_EHIP;
+    }
     return EQFMM_OK;
 }
 
@@ -413,6 +421,9 @@ int eqfmm_plan_destroy(eqfmm_plan *plan)
 {
     if (!plan) return EQFMM_EINVAL;
     for (hipEvent_t e : plan->prof.pool) (void)hipEventDestroy(e);
+    if (plan->ev_bin) (void)hipEventDestroy(plan->ev_bin);
+    if (plan->ev_near) (void)hipEventDestroy(plan->ev_near);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
     delete plan;
     return EQFMM_OK;
 }
