@@ -26,15 +26,17 @@
  * workspace, inputs, outputs).  The library never allocates device memory;
  * it owns only the host-side plan object.  All device pointers are HIP
  * device addresses on the current device; `stream` is a hipStream_t (NULL =
- * default stream).  Work is enqueued on that stream (eqfmm_forward also uses
- * the plan's own stream, joined back into the caller's before the final
- * kernels); eqfmm_forward blocks once per call to read back an 8-byte status
- * (fragment count, error bits).
+ * default stream).  Work is enqueued on that stream (the forward calls also
+ * use the plan's own stream, joined back into the caller's before the final
+ * kernels).  eqfmm_forward blocks once, at its end, to read back a 4-byte
+ * status; eqfmm_forward_async never blocks.
  *
  * Error behaviour: every call returns EQFMM_OK (0) or a negative code.
  * Data-dependent errors (EBOX, ENEUTRAL, ENONFINITE, fragment capacity) are
- * detected on the device and reported by eqfmm_forward; the outputs are then
- * unspecified.  eqfmm_strerror() names a code.
+ * detected on the device; every kernel stays within its buffers whatever the
+ * input (prefix sums are clamped to the fragment capacity), the outputs are
+ * then unspecified, and the code is returned by eqfmm_forward or written to
+ * the status word of eqfmm_forward_async.  eqfmm_strerror() names a code.
  */
 #ifndef EQFMM_H
 #define EQFMM_H
@@ -121,6 +123,18 @@ int eqfmm_workspace_bytes(const eqfmm_plan *plan, int64_t n, size_t *bytes);
 int eqfmm_forward(eqfmm_plan *plan, int64_t n, const double *pos, const double *q,
                   void *phi, void *field, double *energy,
                   void *ws, size_t ws_bytes, void *stream);
+
+/* As eqfmm_forward, but never blocks: the data-dependent status (EQFMM_OK,
+ * EQFMM_EBOX, EQFMM_ENEUTRAL, EQFMM_ENONFINITE or EQFMM_EWORKSPACE) is
+ * written to *status, a device int32, when the enqueued work completes; the
+ * return value covers only the errors found on the host (EINVAL, a
+ * workspace smaller than eqfmm_workspace_bytes, EHIP).  eqfmm_backward may
+ * follow on the same stream at once; its outputs are unspecified if *status
+ * ends up non-zero.  For callers that enqueue many evaluations (serving
+ * loops, graph capture) and check the status when they synchronise. */
+int eqfmm_forward_async(eqfmm_plan *plan, int64_t n, const double *pos, const double *q,
+                        void *phi, void *field, double *energy, int32_t *status,
+                        void *ws, size_t ws_bytes, void *stream);
 
 /* Adjoint of the energy: given dL/dE (device double scalar), writes
  *   dEdx [n][3] = dL/dE * dE/dx_i  and  dEdq [n] = dL/dE * dE/dq_i

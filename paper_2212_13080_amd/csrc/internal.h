@@ -74,8 +74,8 @@ struct WsLayout {
 
 struct WsHeader {
     int32_t flags;        // bit 0 out of box, bit 1 non-finite
-    int32_t pad;
-    int64_t nfrag;        // total fragments (after the scan)
+    int32_t status;       // EQFMM_OK or the data-dependent error of the forward
+    int64_t nfrag;        // total fragments (after the scan, before clamping to capacity)
     double qsum, qabs;    // neutrality check
     double energy;        // reduced energy (mirror of the output)
 };
@@ -107,8 +107,10 @@ int build_image(eqfmm_plan *plan);
 WsLayout ws_layout(const eqfmm_plan *plan, int64_t n);
 
 // launchers (kernels.hip); all enqueue on `st`
+// Enqueues the forward; its status code goes to the header and, if status
+// is not NULL, to *status (device) when the work completes.
 int run_forward(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi,
-                void *field, double *energy, unsigned char *ws, const WsLayout &W, hipStream_t st);
+                void *field, double *energy, int *status, unsigned char *ws, const WsLayout &W, hipStream_t st);
 int run_backward(eqfmm_plan *plan, int64_t n, const double *q, const double *gE, void *dEdx,
                  void *dEdq, unsigned char *ws, const WsLayout &W, hipStream_t st);
 

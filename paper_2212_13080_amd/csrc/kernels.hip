@@ -281,8 +281,11 @@ __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const d
                                               int64_t n, const double *pos, const double *q,
                                               const int *fstart, const int *leafstart, int *cursor,
                                               double *su, double *sv, double *sw, R *sq, int *spar,
-                                              int *sleaf, int *gslot, double *gw, double *gdw)
+                                              int *sleaf, int *gslot, double *gw, double *gdw, int64_t fcap)
 {
+    // Fragments past the capacity fcap are dropped (the forward then reports
+    // EQFMM_EWORKSPACE); the prefix sums are clamped to fcap, so every index
+    // read later stays in range.
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double v[3];
@@ -299,17 +302,21 @@ __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const d
         const int leaf = c[0] + g.D * (c[1] + g.D * c[2]);
         const int slot = leafstart[leaf] + atomicAdd(&cursor[leaf], 1);
         const double s = g.s_leaf;
-        su[slot] = v[0] / s - c[0];
-        sv[slot] = v[1] / s - c[1];
-        sw[slot] = v[2] / s - c[2];
-        sq[slot] = R(qi);
-        spar[slot] = int(i);
-        sleaf[slot] = leaf;
-        gslot[f] = slot;
-        gw[f] = 1.0;
-        gdw[3 * int64_t(f) + 0] = 0.0;
-        gdw[3 * int64_t(f) + 1] = 0.0;
-        gdw[3 * int64_t(f) + 2] = 0.0;
+        if (slot < fcap) {
+            su[slot] = v[0] / s - c[0];
+            sv[slot] = v[1] / s - c[1];
+            sw[slot] = v[2] / s - c[2];
+            sq[slot] = R(qi);
+            spar[slot] = int(i);
+            sleaf[slot] = leaf;
+        }
+        if (f < fcap) {
+            gslot[f] = slot < fcap ? slot : 0;
+            gw[f] = 1.0;
+            gdw[3 * int64_t(f) + 0] = 0.0;
+            gdw[3 * int64_t(f) + 1] = 0.0;
+            gdw[3 * int64_t(f) + 2] = 0.0;
+        }
         return;
     }
     Pieces<N> P[3];
@@ -321,17 +328,21 @@ __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const d
                 const int slot = leafstart[leaf] + atomicAdd(&cursor[leaf], 1);
                 const double ox = P[0].om[kx], oy = P[1].om[ky], oz = P[2].om[kz];
                 const double w = ox * oy * oz;
-                su[slot] = P[0].u[kx];
-                sv[slot] = P[1].u[ky];
-                sw[slot] = P[2].u[kz];
-                sq[slot] = R(qi * w);
-                spar[slot] = int(i);
-                sleaf[slot] = leaf;
-                gslot[f] = slot;
-                gw[f] = w;
-                gdw[3 * int64_t(f) + 0] = P[0].dom[kx] * oy * oz;
-                gdw[3 * int64_t(f) + 1] = ox * P[1].dom[ky] * oz;
-                gdw[3 * int64_t(f) + 2] = ox * oy * P[2].dom[kz];
+                if (slot < fcap) {
+                    su[slot] = P[0].u[kx];
+                    sv[slot] = P[1].u[ky];
+                    sw[slot] = P[2].u[kz];
+                    sq[slot] = R(qi * w);
+                    spar[slot] = int(i);
+                    sleaf[slot] = leaf;
+                }
+                if (f < fcap) {
+                    gslot[f] = slot < fcap ? slot : 0;
+                    gw[f] = w;
+                    gdw[3 * int64_t(f) + 0] = P[0].dom[kx] * oy * oz;
+                    gdw[3 * int64_t(f) + 1] = ox * P[1].dom[ky] * oz;
+                    gdw[3 * int64_t(f) + 2] = ox * oy * P[2].dom[kz];
+                }
             }
 }
 
@@ -388,25 +399,33 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(int *blk, int64_t nb)
     if (threadIdx.x == 0) blk[nb] = carry;
 }
 
-__global__ void __launch_bounds__(256) k_scan_add(int *out, int64_t len, const int *blk, int64_t nb)
+// Adds the block offsets; every prefix (and the total in out[len]) is
+// clamped to clampv, and the unclamped total goes to *total.
+__global__ void __launch_bounds__(256) k_scan_add(int *out, int64_t len, const int *blk, int64_t nb, int clampv,
+                                                  int64_t *total)
 {
     const int64_t base = int64_t(blockIdx.x) * 1024 + threadIdx.x * 4;
     const int add = blk[blockIdx.x];
     for (int k = 0; k < 4; ++k)
-        if (base + k < len) out[base + k] += add;
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[len] = blk[nb];
+        if (base + k < len) {
+            const int v = out[base + k] + add;
+            out[base + k] = v < clampv ? v : clampv;
+        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int tot = blk[nb];
+        out[len] = tot < clampv ? tot : clampv;
+        if (total) *total = tot;
+    }
 }
 
-int scan(const int *in, int *out, int64_t len, int *blk, hipStream_t st)
+// exclusive prefix sums of in[0, len) into out[0, len], clamped to clampv
+int scan(const int *in, int *out, int64_t len, int *blk, int clampv, int64_t *total, hipStream_t st)
 {
     const int64_t nb = (len + 1023) / 1024;
-    if (nb == 0) {
-        EQ_CHECK(hipMemsetAsync(out, 0, sizeof(int), st));
-        return EQFMM_OK;
-    }
+    if (nb == 0) return EQFMM_EINVAL;
     k_scan_local<<<dim3(unsigned(nb)), 256, 0, st>>>(in, out, len, blk);
     k_scan_blocks<<<1, 1024, 0, st>>>(blk, nb);
-    k_scan_add<<<dim3(unsigned(nb)), 256, 0, st>>>(out, len, blk, nb);
+    k_scan_add<<<dim3(unsigned(nb)), 256, 0, st>>>(out, len, blk, nb, clampv, total);
     EQ_CHECK(hipGetLastError());
     return EQFMM_OK;
 }
@@ -600,8 +619,11 @@ __global__ void __launch_bounds__(256) k_gather(int64_t n, const double *q, cons
     if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
 }
 
+// Total energy, and the forward's status from the header: non-finite input,
+// a position outside the box, a non-neutral periodic set, or more fragments
+// than the capacity (in that order).
 __global__ void __launch_bounds__(256) k_energy(const double *epart, int64_t nb, double *energy,
-                                                WsHeader *hdr)
+                                                WsHeader *hdr, int periodic, int64_t fcap, int *status)
 {
     __shared__ double red[256];
     double s = 0.0;
@@ -615,6 +637,14 @@ __global__ void __launch_bounds__(256) k_energy(const double *epart, int64_t nb,
     if (threadIdx.x == 0) {
         hdr->energy = 0.5 * red[0];
         if (energy) *energy = 0.5 * red[0];
+        const int f = hdr->flags;
+        int code = EQFMM_OK;
+        if (f & 2) code = EQFMM_ENONFINITE;
+        else if (f & 1) code = EQFMM_EBOX;
+        else if (periodic && !(fabs(hdr->qsum) <= 1e-10 * hdr->qabs)) code = EQFMM_ENEUTRAL;
+        else if (hdr->nfrag > fcap) code = EQFMM_EWORKSPACE;
+        hdr->status = code;
+        if (status) *status = code;
     }
 }
 
@@ -695,13 +725,13 @@ unsigned blocks(int64_t work, int per) { return unsigned((work + per - 1) / per)
 
 // near field, and far field at the charges (near.hip)
 template <typename R>
-int launch_p2p(const eqfmm_plan *plan, int64_t nfrag, const int *leafstart, const double *su, const double *sv,
-               const double *sw, const R *sq, const int *spar, const int *sleaf, const unsigned char *smask,
-               double *sphi, double *snf, hipStream_t st);
+int launch_p2p(const eqfmm_plan *plan, int64_t n, int64_t fcap, const int *leafstart, const double *su,
+               const double *sv, const double *sw, const R *sq, const int *spar, const int *sleaf,
+               const unsigned char *smask, double *sphi, double *snf, hipStream_t st);
 template <int N, typename R>
-int launch_l2p(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const double *su, const double *sv,
-               const double *sw, const int *spar, const int *sleaf, const unsigned char *smask, const R *locL,
-               double *sphi, const double *snf, R *sfld, hipStream_t st);
+int launch_l2p(const eqfmm_plan *plan, int64_t fcap, const int *leafstart, const R *t, const R *den,
+               const double *su, const double *sv, const double *sw, const int *spar, const int *sleaf,
+               const unsigned char *smask, const R *locL, double *sphi, const double *snf, R *sfld, hipStream_t st);
 
 // far field (declared here, defined with the matrix-core kernels in m2l.hip):
 // the haloed copy of Phi at levels lmin..lmax, then the products of every
@@ -715,7 +745,7 @@ int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const i
 
 template <int N, typename R>
 int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi_out,
-                 void *fld_out, double *energy, unsigned char *ws, const WsLayout &W, hipStream_t st)
+                 void *fld_out, double *energy, int *status, unsigned char *ws, const WsLayout &W, hipStream_t st)
 {
     using O = Ord<N>;
     const Geom &g = plan->g;
@@ -732,28 +762,21 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     k_count<N><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, n, pos, q, v.cnt, v.fstart, v.smask, v.leafcnt,
                                                  v.hdr);
     EQ_CHECK(hipGetLastError());
+    // every prefix is clamped to the fragment capacity: a set that needs more
+    // runs on in range and reports EQFMM_EWORKSPACE
+    const int fcap = int(W.fcap);
     int rc = EQFMM_OK;
     if (g.continuous) {   // fragments per charge vary only in the split modes
-        rc = scan(v.cnt, v.fstart, n, v.scanblk, st);
+        rc = scan(v.cnt, v.fstart, n, v.scanblk, fcap, nullptr, st);
         if (rc) return rc;
     }
-    rc = scan(v.leafcnt, v.leafstart, nleaf, v.scanblk, st);
+    rc = scan(v.leafcnt, v.leafstart, nleaf, v.scanblk, fcap, &v.hdr->nfrag, st);
     if (rc) return rc;
-    WsHeader h;
-    int nfrag = int(n);   // one fragment per charge unless split
-    EQ_CHECK(hipMemcpyAsync(&h, v.hdr, sizeof(WsHeader), hipMemcpyDeviceToHost, st));
-    if (g.continuous) EQ_CHECK(hipMemcpyAsync(&nfrag, v.fstart + n, sizeof(int), hipMemcpyDeviceToHost, st));
-    EQ_CHECK(hipStreamSynchronize(st));
-    if (h.flags & 2) return EQFMM_ENONFINITE;
-    if (h.flags & 1) return EQFMM_EBOX;
-    if (g.periodic && !(fabs(h.qsum) <= 1e-10 * h.qabs)) return EQFMM_ENEUTRAL;
-    if (nfrag > W.fcap) return EQFMM_EWORKSPACE;
-    plan->last_nfrag = nfrag;
     k_emit<N, R><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, ops.seg_den64, n, pos, q, v.fstart,
                                                  v.leafstart, v.cursor, v.su, v.sv, v.sw, v.sq,
-                                                 v.spar, v.sleaf, v.gslot, v.gw, v.gdw);
+                                                 v.spar, v.sleaf, v.gslot, v.gw, v.gdw, W.fcap);
     EQ_CHECK(hipGetLastError());
-    prof_end(plan, st, pk, EQFMM_STAGE_BIN, 0.0, double(n) * 64.0 + double(nfrag) * 40.0);
+    prof_end(plan, st, pk, EQFMM_STAGE_BIN, 0.0, double(n) * 104.0);
 
     // a8: near field on the side stream, concurrent with a3-a6
     hipStream_t sd = plan->side;
@@ -761,8 +784,8 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     EQ_CHECK(hipEventRecord(plan->ev_bin, st));
     EQ_CHECK(hipStreamWaitEvent(sd, plan->ev_bin, 0));
     pk = prof_begin(plan, sd);
-    rc = launch_p2p<R>(plan, nfrag, v.leafstart, v.su, v.sv, v.sw, v.sq, v.spar, v.sleaf, v.smask, v.sphi, v.snf,
-                       sd);
+    rc = launch_p2p<R>(plan, n, W.fcap, v.leafstart, v.su, v.sv, v.sw, v.sq, v.spar, v.sleaf, v.smask, v.sphi,
+                       v.snf, sd);
     if (rc) return rc;
     prof_end(plan, sd, pk, EQFMM_STAGE_LEAF, 0.0, 0.0);
     EQ_CHECK(hipEventRecord(plan->ev_near, sd));
@@ -777,8 +800,8 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
                                                         v.sq, v.phi + W.lvl[L] * O::NS);
         EQ_CHECK(hipGetLastError());
     }
-    prof_end(plan, st, pk, EQFMM_STAGE_P2M, double(nfrag) * (2.0 * O::N3 + 9.0 * N),
-             double(nfrag) * 4 * rs + double(nleaf) * O::NS * rs);
+    prof_end(plan, st, pk, EQFMM_STAGE_P2M, double(n) * (2.0 * O::N3 + 9.0 * N),
+             double(n) * 4 * rs + double(nleaf) * O::NS * rs);
 
     // a4: upward pass; free space needs Phi down to level 2, periodic to 0
     const int lmin = g.periodic ? 1 : 2;
@@ -818,8 +841,8 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     // a7: far field at the fragments, added to the near-field sums
     EQ_CHECK(hipStreamWaitEvent(st, plan->ev_near, 0));
     pk = prof_begin(plan, st);
-    rc = launch_l2p<N, R>(plan, nfrag, t, den, v.su, v.sv, v.sw, v.spar, v.sleaf, v.smask, v.loc + W.lvl[L] * O::NS,
-                          v.sphi, v.snf, v.sfld, st);
+    rc = launch_l2p<N, R>(plan, W.fcap, v.leafstart, t, den, v.su, v.sv, v.sw, v.spar, v.sleaf, v.smask,
+                          v.loc + W.lvl[L] * O::NS, v.sphi, v.snf, v.sfld, st);
     if (rc) return rc;
     prof_end(plan, st, pk, EQFMM_STAGE_LEAF, 0.0, 0.0);
 
@@ -829,7 +852,7 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
                                                             v.gdw, v.sphi, v.sfld,
                                                             static_cast<R *>(phi_out),
                                                             static_cast<R *>(fld_out), v.epart);
-    k_energy<<<1, 256, 0, st>>>(v.epart, W.e_blocks, energy, v.hdr);
+    k_energy<<<1, 256, 0, st>>>(v.epart, W.e_blocks, energy, v.hdr, g.periodic, W.fcap, status);
     EQ_CHECK(hipGetLastError());
     prof_end(plan, st, pk, EQFMM_STAGE_GATHER, 0.0, 0.0);
     return EQFMM_OK;
@@ -863,15 +886,18 @@ int backward_impl(eqfmm_plan *plan, int64_t n, const double *q, const double *gE
     }
 
 int run_forward(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi,
-                void *field, double *energy, unsigned char *ws, const WsLayout &W, hipStream_t st)
+                void *field, double *energy, int *status, unsigned char *ws, const WsLayout &W, hipStream_t st)
 {
     if (n == 0) {
         if (energy) EQ_CHECK(hipMemsetAsync(energy, 0, sizeof(double), st));
+        EQ_CHECK(hipMemsetAsync(ws + W.hdr, 0, sizeof(WsHeader), st));
+        if (status) EQ_CHECK(hipMemsetAsync(status, 0, sizeof(int), st));
         return EQFMM_OK;
     }
     if (plan->p.precision == EQFMM_FP64)
-        EQ_ORDER_SWITCH(plan->g.n, (forward_impl<N, double>(plan, n, pos, q, phi, field, energy, ws, W, st)))
-    EQ_ORDER_SWITCH(plan->g.n, (forward_impl<N, float>(plan, n, pos, q, phi, field, energy, ws, W, st)))
+        EQ_ORDER_SWITCH(plan->g.n,
+                        (forward_impl<N, double>(plan, n, pos, q, phi, field, energy, status, ws, W, st)))
+    EQ_ORDER_SWITCH(plan->g.n, (forward_impl<N, float>(plan, n, pos, q, phi, field, energy, status, ws, W, st)))
 }
 
 int run_backward(eqfmm_plan *plan, int64_t n, const double *q, const double *gE, void *dEdx,

@@ -398,13 +398,13 @@ __global__ void __launch_bounds__(256) k_near(Geom g, int RB, const int *leafsta
 // sorted fragments: the lanes of a wave then mostly share a cell, so every
 // source load is a broadcast, and a large cluster spreads over many waves.
 template <typename R>
-__global__ void __launch_bounds__(256) k_near_dense(Geom g, int RB, int64_t nfrag, const int *leafstart,
+__global__ void __launch_bounds__(256) k_near_dense(Geom g, int RB, const int *nfrag, const int *leafstart,
                                                     const double *su, const double *sv, const double *sw,
                                                     const R *sq, const int *spar, const int *sleaf,
                                                     const unsigned char *smask, double *sphi, double *snf)
 {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= nfrag) return;
+    if (t >= *nfrag) return;
     const int D = g.D;
     const int leaf = sleaf[t];
     const int tx = leaf % D, row = leaf / D, y = row % D, z = row / D;
@@ -441,14 +441,14 @@ __global__ void __launch_bounds__(256) k_near_dense(Geom g, int RB, int64_t nfra
 // the fragment's finest cell evaluated on the replacement of a unit charge
 // there, and its gradient.
 template <int N, typename R>
-__global__ void __launch_bounds__(256) k_l2p(Geom g, const R *t_, const R *den_, int64_t nfrag, const double *su,
+__global__ void __launch_bounds__(256) k_l2p(Geom g, const R *t_, const R *den_, const int *nfrag, const double *su,
                                              const double *sv, const double *sw, const int *spar,
                                              const int *sleaf, const unsigned char *smask, const R *locL,
                                              double *sphi, const double *snf, R *sfld)
 {
     using O = NearShape<N>;
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= nfrag) return;
+    if (t >= *nfrag) return;
     const double sd = g.s_leaf;
     const double ud = su[t], vd = sv[t], wd = sw[t];
     const bool dbl = sizeof(R) == sizeof(float) && g.continuous && smask[spar[t]];
@@ -472,13 +472,16 @@ __global__ void __launch_bounds__(256) k_l2p(Geom g, const R *t_, const R *den_,
 }  // namespace
 
 // cells per workgroup row block: about 64 targets on average
+// n: charges (sets the row-block size); fcap: fragment capacity (grid of
+// the dense kernel, which reads the actual count from leafstart[D^3])
 template <typename R>
-int launch_p2p(const eqfmm_plan *plan, int64_t nfrag, const int *leafstart, const double *su, const double *sv,
-               const double *sw, const R *sq, const int *spar, const int *sleaf, const unsigned char *smask,
-               double *sphi, double *snf, hipStream_t st)
+int launch_p2p(const eqfmm_plan *plan, int64_t n, int64_t fcap, const int *leafstart, const double *su,
+               const double *sv, const double *sw, const R *sq, const int *spar, const int *sleaf,
+               const unsigned char *smask, double *sphi, double *snf, hipStream_t st)
 {
     const Geom &g = plan->g;
-    const double mean = double(nfrag) / (double(g.D) * g.D * g.D);
+    const int64_t nleaf = int64_t(g.D) * g.D * g.D;
+    const double mean = double(n) / double(nleaf);
     int RB = int(64.0 / (mean > 1e-9 ? mean : 1e-9) + 0.5);
     RB = RB < 1 ? 1 : (RB > g.D ? g.D : RB);
     RB = RB > kMaxRB ? kMaxRB : RB;
@@ -486,34 +489,37 @@ int launch_p2p(const eqfmm_plan *plan, int64_t nfrag, const int *leafstart, cons
     const int64_t grid = int64_t(g.D) * g.D * nxb;
     k_near<R><<<dim3(unsigned(grid)), 256, 0, st>>>(g, RB, leafstart, su, sv, sw, sq, spar, sleaf, smask, sphi,
                                                     snf);
-    if (nfrag > 0)
-        k_near_dense<R><<<dim3(unsigned((nfrag + 255) / 256)), 256, 0, st>>>(g, RB, nfrag, leafstart, su, sv, sw,
-                                                                            sq, spar, sleaf, smask, sphi, snf);
+    if (fcap > 0)
+        k_near_dense<R><<<dim3(unsigned((fcap + 255) / 256)), 256, 0, st>>>(g, RB, leafstart + nleaf, leafstart, su,
+                                                                           sv, sw, sq, spar, sleaf, smask, sphi,
+                                                                           snf);
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
 
 template <int N, typename R>
-int launch_l2p(const eqfmm_plan *plan, int64_t nfrag, const R *t, const R *den, const double *su, const double *sv,
-               const double *sw, const int *spar, const int *sleaf, const unsigned char *smask, const R *locL,
-               double *sphi, const double *snf, R *sfld, hipStream_t st)
+int launch_l2p(const eqfmm_plan *plan, int64_t fcap, const int *leafstart, const R *t, const R *den,
+               const double *su, const double *sv, const double *sw, const int *spar, const int *sleaf,
+               const unsigned char *smask, const R *locL, double *sphi, const double *snf, R *sfld, hipStream_t st)
 {
-    if (nfrag > 0)
-        k_l2p<N, R><<<dim3(unsigned((nfrag + 255) / 256)), 256, 0, st>>>(plan->g, t, den, nfrag, su, sv, sw, spar,
-                                                                         sleaf, smask, locL, sphi, snf, sfld);
+    const int64_t nleaf = int64_t(plan->g.D) * plan->g.D * plan->g.D;
+    if (fcap > 0)
+        k_l2p<N, R><<<dim3(unsigned((fcap + 255) / 256)), 256, 0, st>>>(plan->g, t, den, leafstart + nleaf, su, sv,
+                                                                        sw, spar, sleaf, smask, locL, sphi, snf,
+                                                                        sfld);
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
 
-template int launch_p2p<float>(const eqfmm_plan *, int64_t, const int *, const double *, const double *,
+template int launch_p2p<float>(const eqfmm_plan *, int64_t, int64_t, const int *, const double *, const double *,
                                const double *, const float *, const int *, const int *, const unsigned char *,
                                double *, double *, hipStream_t);
-template int launch_p2p<double>(const eqfmm_plan *, int64_t, const int *, const double *, const double *,
+template int launch_p2p<double>(const eqfmm_plan *, int64_t, int64_t, const int *, const double *, const double *,
                                 const double *, const double *, const int *, const int *, const unsigned char *,
                                 double *, double *, hipStream_t);
 #define EQ_L2P_INST(NN, RR)                                                                                  \
-    template int launch_l2p<NN, RR>(const eqfmm_plan *, int64_t, const RR *, const RR *, const double *,      \
-                                    const double *, const double *, const int *, const int *,               \
-                                    const unsigned char *, const RR *, double *, const double *, RR *,      \
-                                    hipStream_t);
+    template int launch_l2p<NN, RR>(const eqfmm_plan *, int64_t, const int *, const RR *, const RR *,         \
+                                    const double *, const double *, const double *, const int *,            \
+                                    const int *, const unsigned char *, const RR *, double *,               \
+                                    const double *, RR *, hipStream_t);
 EQ_L2P_INST(2, float) EQ_L2P_INST(3, float) EQ_L2P_INST(4, float) EQ_L2P_INST(5, float)
 EQ_L2P_INST(6, float) EQ_L2P_INST(7, float)
 EQ_L2P_INST(2, double) EQ_L2P_INST(3, double) EQ_L2P_INST(4, double) EQ_L2P_INST(5, double)

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 
@@ -234,7 +235,8 @@ WsLayout ws_layout(const eqfmm_plan *plan, int64_t n)
         W.fcap = plan->p.max_fragments > 0 ? plan->p.max_fragments : 2 * n + 4096;
     else
         W.fcap = n;
-    W.fcap = std::max<int64_t>(W.fcap, 1);
+    // fragment indices are 32-bit
+    W.fcap = std::min<int64_t>(std::max<int64_t>(W.fcap, 1), int64_t(INT32_MAX) - 1);
     W.lvl.resize(g.L + 2);
     W.lvl[0] = 0;
     for (int l = 0; l <= g.L; ++l) W.lvl[l + 1] = W.lvl[l] + (int64_t(1) << (3 * l));
@@ -387,22 +389,47 @@ int eqfmm_workspace_bytes(const eqfmm_plan *plan, int64_t n, size_t *bytes)
     return EQFMM_OK;
 }
 
-int eqfmm_forward(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi,
-                  void *field, double *energy, void *ws, size_t ws_bytes, void *stream)
+namespace {
+
+int forward_common(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi, void *field,
+                   double *energy, int32_t *status, void *ws, size_t ws_bytes, void *stream, bool wait)
 {
     if (!plan || !plan->dev || n < 0 || n > (int64_t(1) << 30)) return EQFMM_EINVAL;
     if (n > 0 && (!pos || !q)) return EQFMM_EINVAL;
-    if (!ws) return EQFMM_EINVAL;
+    if (!ws || (!wait && !status)) return EQFMM_EINVAL;
     WsLayout W = ws_layout(plan, n);
     if (ws_bytes < W.total) return EQFMM_EWORKSPACE;
     plan->last_ws = nullptr;
-    int rc = run_forward(plan, n, pos, q, phi, field, energy, static_cast<unsigned char *>(ws), W,
-                         static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    int rc = run_forward(plan, n, pos, q, phi, field, energy, status, w, W, st);
+    if (rc == EQFMM_OK && wait) {
+        int32_t code = 0;
+        const WsHeader *hdr = reinterpret_cast<const WsHeader *>(w + W.hdr);
+        if (hipMemcpyAsync(&code, &hdr->status, sizeof(code), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return EQFMM_EHIP;
+        rc = code;
+    }
     if (rc == EQFMM_OK) {
         plan->last_ws = ws;
         plan->last_n = n;
     }
     return rc;
+}
+
+}  // namespace
+
+int eqfmm_forward(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi,
+                  void *field, double *energy, void *ws, size_t ws_bytes, void *stream)
+{
+    return forward_common(plan, n, pos, q, phi, field, energy, nullptr, ws, ws_bytes, stream, true);
+}
+
+int eqfmm_forward_async(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi,
+                        void *field, double *energy, int32_t *status, void *ws, size_t ws_bytes, void *stream)
+{
+    return forward_common(plan, n, pos, q, phi, field, energy, status, ws, ws_bytes, stream, false);
 }
 
 int eqfmm_backward(eqfmm_plan *plan, int64_t n, const double *q, const double *grad_energy,

@@ -35,6 +35,8 @@ class Plan:
         self.params = p
         self.levels, self.order, self.boundary, self.precision = levels, order, boundary, precision
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.handle = native.eqfmm_plan_create(p)
         nbytes = native.eqfmm_plan_device_bytes(self.handle)
         self._dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
@@ -63,7 +65,10 @@ class Plan:
         return ws
 
     # raw calls ------------------------------------------------------------
-    def forward(self, pos, q, want_phi=True, want_field=True, ws=None):
+    def forward(self, pos, q, want_phi=True, want_field=True, ws=None, status=None):
+        """E, phi, field of the charges.  With `status` (a device int32
+        tensor of one element) the call does not wait for the GPU: the
+        data-dependent status code lands in `status` (see `check_status`)."""
         pos = pos.detach().to(self.device, torch.float64).contiguous()
         q = q.detach().to(self.device, torch.float64).contiguous()
         n = q.numel()
@@ -73,9 +78,23 @@ class Plan:
         phi = torch.empty(n, dtype=self.dtype, device=self.device) if want_phi else None
         field = torch.empty((n, 3), dtype=self.dtype, device=self.device) if want_field else None
         E = torch.empty((), dtype=torch.float64, device=self.device)
-        native.eqfmm_forward(self.handle, n, pos.data_ptr(), q.data_ptr(), _ptr(phi), _ptr(field),
-                             E.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+        if status is None:
+            native.eqfmm_forward(self.handle, n, pos.data_ptr(), q.data_ptr(), _ptr(phi), _ptr(field),
+                                 E.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+        else:
+            if status.dtype != torch.int32 or status.numel() != 1 or status.device != self.device:
+                raise ValueError("status must be one int32 on the plan's device")
+            native.eqfmm_forward_async(self.handle, n, pos.data_ptr(), q.data_ptr(), _ptr(phi), _ptr(field),
+                                       E.data_ptr(), status.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
         return E, phi, field
+
+    @staticmethod
+    def check_status(status):
+        """Raise EqfmmError if the status word of an asynchronous forward
+        holds an error (synchronises with it)."""
+        code = int(status.item())
+        if code != 0:
+            raise native.EqfmmError(code, "eqfmm_forward_async")
 
     def backward(self, q, grad_E, ws=None, want_dx=True, want_dq=True):
         q = q.detach().to(self.device, torch.float64).contiguous()

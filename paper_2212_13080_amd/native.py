@@ -23,8 +23,9 @@ _ERR = {0: "EQFMM_OK", -1: "EQFMM_EINVAL", -2: "EQFMM_EBOX", -3: "EQFMM_ENEUTRAL
         -4: "EQFMM_ENONFINITE", -5: "EQFMM_EWORKSPACE", -6: "EQFMM_EHIP", -7: "EQFMM_ESTATE"}
 
 EXPORTS = ("eqfmm_plan_create", "eqfmm_plan_device_bytes", "eqfmm_plan_upload",
-           "eqfmm_workspace_bytes", "eqfmm_forward", "eqfmm_backward", "eqfmm_plan_destroy",
-           "eqfmm_strerror", "eqfmm_profile_enable", "eqfmm_profile_read", "eqfmm_version")
+           "eqfmm_workspace_bytes", "eqfmm_forward", "eqfmm_forward_async", "eqfmm_backward",
+           "eqfmm_plan_destroy", "eqfmm_strerror", "eqfmm_profile_enable", "eqfmm_profile_read",
+           "eqfmm_version")
 
 
 class EqfmmError(RuntimeError):
@@ -60,6 +61,8 @@ def lib():
         L.eqfmm_plan_upload.argtypes = [_VP, _VP, ctypes.c_size_t, _VP]
         L.eqfmm_workspace_bytes.argtypes = [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
         L.eqfmm_forward.argtypes = [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+        L.eqfmm_forward_async.argtypes = [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                          ctypes.c_size_t, _VP]
         L.eqfmm_backward.argtypes = [_VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
         L.eqfmm_plan_destroy.argtypes = [_VP]
         L.eqfmm_strerror.argtypes = [ctypes.c_int]
@@ -105,6 +108,12 @@ def eqfmm_workspace_bytes(plan, n: int) -> int:
 def eqfmm_forward(plan, n, pos_ptr, q_ptr, phi_ptr, field_ptr, energy_ptr, ws_ptr, ws_bytes, stream):
     check(lib().eqfmm_forward(plan, n, pos_ptr, q_ptr, phi_ptr, field_ptr, energy_ptr, ws_ptr,
                               ws_bytes, stream), "eqfmm_forward")
+
+
+def eqfmm_forward_async(plan, n, pos_ptr, q_ptr, phi_ptr, field_ptr, energy_ptr, status_ptr, ws_ptr, ws_bytes,
+                        stream):
+    check(lib().eqfmm_forward_async(plan, n, pos_ptr, q_ptr, phi_ptr, field_ptr, energy_ptr, status_ptr, ws_ptr,
+                                    ws_bytes, stream), "eqfmm_forward_async")
 
 
 def eqfmm_backward(plan, n, q_ptr, grad_ptr, dEdx_ptr, dEdq_ptr, ws_ptr, ws_bytes, stream):

@@ -174,6 +174,63 @@ def test_error_codes():
     assert np.isfinite(E.item())
 
 
+@pytest.mark.parametrize("case", [("c1", 4096, 3, 4, FREE), ("c3", 8000, 3, 5, PER_C), ("c4", 4096, 3, 6, FREE_C)],
+                         ids=lambda c: f"{c[0]}-b{c[4]}")
+def test_async_forward_parity(case):
+    """eqfmm_forward_async: status 0 and the FP32 parity bar against the
+    oracle, with the adjoint enqueued right behind it."""
+    key, n, levels, order, boundary = case
+    print(f"case {case}", flush=True)
+    pos, q, r = oracle_result(key, n, levels, order, boundary)
+    plan = eq.Plan(levels, order, boundary, eq.FP32)
+    pt, qt = torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda()
+    status = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    E, phi, field = plan.forward(pt, qt, status=status)
+    dx, dq = plan.backward(qt, torch.ones((), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    g = dict(energy=E.item(), phi=phi.double().cpu().numpy(), field=field.double().cpu().numpy(),
+             dEdx=dx.double().cpu().numpy(), dEdq=dq.double().cpu().numpy())
+    check(g, r, q, TOL[eq.FP32], f"{key} async")
+
+
+def test_async_error_status():
+    """Data-dependent errors through the status word; the kernels stay in
+    range whatever the input, and the plan keeps working afterwards."""
+    rng = np.random.default_rng(6)
+    pos = torch.from_numpy(rng.random((100, 3))).cuda()
+    q = torch.from_numpy(rng.uniform(-1, 1, 100)).cuda()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def code(plan, p, qq):
+        status.fill_(99)
+        plan.forward(p, qq, status=status)
+        torch.cuda.synchronize()
+        return status.item()
+
+    plan = eq.Plan(3, 4, FREE, eq.FP32)
+    assert code(plan, pos + 1.5, q) == -2
+    bad = pos.clone()
+    bad[3, 0] = float("inf")
+    assert code(plan, bad, q) == -4
+    assert code(eq.Plan(3, 4, PER, eq.FP32), pos, q.abs()) == -3
+    small = eq.Plan(3, 4, FREE_C, eq.FP32, split_d=0.02, max_fragments=101)
+    assert code(small, pos, q) == -5
+    with pytest.raises(eq.EqfmmError) as e:
+        eq.Plan.check_status(status)
+    assert e.value.code == -5
+    # a set that fits the same small capacity (charges near finest-cell
+    # centres, so none is split) is computed correctly
+    cells = rng.integers(0, 8, (8, 3))
+    inner = torch.from_numpy((cells + 0.5 + rng.uniform(-0.08, 0.08, (8, 3))) / 8.0).cuda()
+    qi = torch.from_numpy(rng.uniform(-1, 1, 8)).cuda()
+    assert code(small, inner, qi) == 0
+    E, phi, _ = small.forward(inner, qi)
+    ref = oracle.fmm(inner.cpu().numpy(), qi.cpu().numpy(), 3, 4, FREE_C, split_d=0.02)
+    assert abs(E.item() - ref["energy"]) <= 1e-5 * 0.5 * np.abs(qi.cpu().numpy() * ref["phi"]).sum()
+    assert code(plan, pos, q) == 0
+
+
 def test_autograd_matches_oracle_and_finite_differences():
     # energy via forward, dE/dx and dE/dq via the adjoint kernel
     w, pos, q = case_inputs("c2", 8192, 3)
