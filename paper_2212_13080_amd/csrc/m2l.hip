@@ -4,11 +4,12 @@
 // Work decomposition: every target cell with the same parity p (cell index
 // mod 2 per axis) has the same interaction list, the 189 displacements o in
 // [-2-p, 3-p]^3 minus the 27 adjacent ones (children of the parent's
-// neighbours that are not adjacent), padded to kListLen with zero matrices.  A wave owns 32 target cells of one
-// parity (the same child of 32 parents that are consecutive in Morton order,
-// a 4x4x2 block) and one 32-wide block of target nodes, and runs through the
-// interaction list; for each displacement the 32 source rows form the A
-// operand and the matching rows of K_o the B operand of a
+// neighbours that are not adjacent), padded to kListLen with zero matrices.
+// A wave owns 32 target cells of one parity (the same child of 32 parents
+// that are consecutive in Morton order, a 4x4x2 block) and one 32-wide block
+// of target nodes, and runs through the interaction list; for each
+// displacement the 32 source rows form the A operand and the matching rows
+// of K_o the B operand of a
 //   C[cell][node] += sum_k Phi_src(cell)[k] K_o[node][k]
 // product.  The source-node axis k is split in two halves, one per half
 // wave, so that each lane streams one contiguous half row of Phi and of K_o.
@@ -172,206 +173,6 @@ __global__ void __launch_bounds__(256) k_m2l_pad(MxPad pd, int periodic, const V
 
 // --------------------------------------------------------------- kernels
 
-// grid: ceil(8 * NB * ntile / TPW) workgroups of 4 waves per level (rounded
-// up to 8 overall); work items (tile, parity, node block) are numbered with
-// the node block fastest and the tile slowest, and the workgroup id is
-// remapped so that each of the 8 XCDs gets a contiguous range of them: a
-// compact region of space whose targets of all parities share their
-// sources in that XCD's L2.
-//
-// Sources are read from the haloed copy of Phi, where the source of every
-// target of a tile lies at the same row distance for a given displacement:
-// the address of a step is a wave-uniform base (scalar registers) plus a
-// per-lane offset fixed for the whole list, and no bounds tests are needed.
-//
-// The walk over (displacement, k-chunk) steps is software pipelined: the
-// operands of step s+1 are loaded into the second register stage while the
-// matrix cores work on step s.  Each displacement's product goes to a fresh
-// accumulator pair that is added to float running sums when the
-// displacement is complete.
-template <int N, bool BF16, int CH, int NSPLIT, int NST>
-__global__ void __launch_bounds__(256) k_m2l_mx(const void *__restrict__ Kmx, const int *__restrict__ mxtab,
-                                                MxLevels lv, const float *__restrict__ phipad,
-                                                float *__restrict__ loc_all, int nwg)
-{
-    using S = MxShape<N>;
-    constexpr int NS = S::NS, KH = S::KH, NB = S::NB;
-    constexpr int NA = KH / 4;            // float4 loads of one half row
-    constexpr int NCH = NA / CH;          // pipeline steps per displacement
-    static_assert(NA % CH == 0, "chunking");
-    static_assert(!BF16 || CH % 2 == 0, "bf16 steps take 8 sources per lane");
-    using BT = typename std::conditional<BF16, bf16x8, float4>::type;
-    constexpr int NBL = BF16 ? CH / 2 : CH;   // B loads per step
-    constexpr int NBK = BF16 ? NA / 2 : NA;   // B vectors per lane, node block and displacement
-    const int per = gridDim.x >> 3;
-    int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (wg >= nwg) return;
-    int li = 0;
-    while (li + 1 < lv.nlev && wg >= lv.wg_begin[li + 1]) ++li;
-    wg -= lv.wg_begin[li];
-    const int level = lv.level[li], ntile = lv.ntile[li];
-    const float inv_side = lv.inv_side[li];
-    float *loc = loc_all + lv.cell0[li] * NS;
-    // a workgroup of 4 waves holds TPW = 4 / NSPLIT work items (tile, node
-    // block), node block fastest: the node blocks of a tile then read its
-    // sources at the same time.  NSPLIT waves share one item, each running a
-    // contiguous part of the interaction list, and their sums are added in a
-    // fixed order at the end.
-    constexpr int TPW = 4 / NSPLIT;
-    const int nitem = ntile * 8 * NB;
-    const int lane = threadIdx.x & 63;
-    // wave index as a uniform value: the tile, list range and addresses
-    // derived from it then live in scalar registers
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int it = wg * TPW + wv % TPW;
-    const int tp = it / NB, nb = it - tp * NB;
-    const int t = tp >> 3, p = tp & 7;
-    const int hs = wv / TPW;
-    constexpr int OPS = kListLen / NSPLIT;           // even: displacements go in pairs
-    static_assert(kListLen % (2 * NSPLIT) == 0, "list padding");
-    const int o_begin = hs * OPS, o_end = o_begin + OPS;
-    const bool active = it < nitem;
-    const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
-    const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
-    const int64_t nparent = int64_t(Dp) * Dp * Dp;
-    const int i = lane & 31, gh = lane >> 5;
-    // the tile's 32 parents are consecutive in Morton order, a 4x4x2 block
-    // whose first parent is its lowest corner; lanes past the last parent
-    // (coarse levels) read the corner's sources and store nothing
-    const int64_t Pm0 = int64_t(t) * 32, Pm = Pm0 + i;
-    const int64_t Pl = Pm < nparent ? Pm : Pm0;
-    const int x0 = 2 * compact3(Pm0) + px, y0 = 2 * compact3(Pm0 >> 1) + py, z0 = 2 * compact3(Pm0 >> 2) + pz;
-    const int cx = 2 * compact3(Pl) + px, cy = 2 * compact3(Pl >> 1) + py, cz = 2 * compact3(Pl >> 2) + pz;
-    const float *phi0 =
-        phipad + (lv.pcell0[li] + (int64_t(z0 + kHalo) * P + (y0 + kHalo)) * P + (x0 + kHalo)) * NS;
-    const uint32_t voff = uint32_t((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + gh * KH) * 4u;
-    // the lists of the 8 parities at this level, in LDS (entries read as
-    // uniform values)
-    __shared__ int stab[8 * kListLen];
-    for (int k = threadIdx.x; k < 8 * kListLen; k += 256) stab[k] = mxtab[level * 8 * kListLen + k];
-    __syncthreads();
-    const int *ptab = stab + p * kListLen;
-    const char *kb = static_cast<const char *>(Kmx) + size_t(nb) * NBK * 64 * sizeof(BT);
-    const uint32_t boff = uint32_t(lane) * uint32_t(sizeof(BT));
-
-    float4 abuf[NST][CH];
-    BT bbuf[NST][NBL];
-
-    // Loads of step `step` (clamped, so that the loop body is branch free and
-    // the wait counts stay exact).
-    auto issue = [&](int step, auto bc) {
-        constexpr int b = decltype(bc)::value;
-        step = step < o_end * NCH ? step : o_end * NCH - 1;   // prefetch past the end
-        const int oidx = step / NCH, ch = step - oidx * NCH;
-        const int e = __builtin_amdgcn_readfirstlane(ptab[oidx]);
-        const int oi = e & 511, delta = e >> 9;
-        const float4 *ap =
-            reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS) + voff) +
-            ch * CH;
-#pragma unroll
-        for (int c = 0; c < CH; ++c) abuf[b][c] = ap[c];
-        const BT *bp = reinterpret_cast<const BT *>(kb + size_t(oi) * (NB * NBK * 64 * sizeof(BT)) + boff) +
-                       ch * NBL * 64;
-#pragma unroll
-        for (int c = 0; c < NBL; ++c) bbuf[b][c] = bp[c * 64];
-    };
-
-    // Two accumulator pairs, alternating by displacement: the pair of
-    // displacement d is added to the running sums while the products of
-    // displacement d + 1 are under way, not after a drain of the matrix cores.
-    floatx16 ca0 = {}, ca1 = {}, cb0 = {}, cb1 = {}, run = {};
-    // one k-chunk of one displacement from register stage b into (x0, x1)
-    auto compute = [&](auto bc, floatx16 &x0, floatx16 &x1) {
-        constexpr int b = decltype(bc)::value;
-        if constexpr (!BF16) {
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const float4 a = abuf[b][c];
-                const float4 bb = bbuf[b][c];
-                x0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bb.x, x0, 0, 0, 0);
-                x1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bb.y, x1, 0, 0, 0);
-                x0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bb.z, x0, 0, 0, 0);
-                x1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bb.w, x1, 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < NBL; ++c) {
-                const float4 a0 = abuf[b][2 * c], a1 = abuf[b][2 * c + 1];
-                bf16x8 a;
-                a[0] = __bf16(a0.x);
-                a[1] = __bf16(a0.y);
-                a[2] = __bf16(a0.z);
-                a[3] = __bf16(a0.w);
-                a[4] = __bf16(a1.x);
-                a[5] = __bf16(a1.y);
-                a[6] = __bf16(a1.z);
-                a[7] = __bf16(a1.w);
-                if (c & 1) x1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], x1, 0, 0, 0);
-                else x0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bbuf[b][c], x0, 0, 0, 0);
-            }
-        }
-    };
-
-    // NST register stages: the loads of step s + NST - 1 are issued before the
-    // products of step s.  A trip covers TS steps, a multiple of NCH and NST
-    // holding an even number of displacements, unrolled at compile time so
-    // that the stage and accumulator pair of every step are constants and the
-    // body has no branches.
-    constexpr int TS0 = lcm_c(NCH, NST);
-    constexpr int TS = (TS0 / NCH) % 2 ? 2 * TS0 : TS0, TD = TS / NCH;
-    static_assert(OPS % TD == 0 && (OPS * NCH) % NST == 0, "pipeline trip");
-    if (active) {
-        static_for<0, NST - 1>([&](auto J) {
-            constexpr int j = decltype(J)::value;
-            issue(o_begin * NCH + j, std::integral_constant<int, j>{});
-        });
-        for (int op = o_begin; op < o_end; op += TD) {
-            static_for<0, TS>([&](auto J) {
-                constexpr int j = decltype(J)::value;
-                constexpr int b = j % NST;
-                constexpr int ch = j % NCH;
-                constexpr bool odd = (j / NCH) & 1;
-                issue(op * NCH + j + NST - 1, std::integral_constant<int, (j + NST - 1) % NST>{});
-                // keep the loads of the later steps ahead of this step's products
-                __builtin_amdgcn_sched_barrier(0);
-                if constexpr (odd) {
-                    if constexpr (ch == 0) cb0 = cb1 = floatx16{};
-                    compute(std::integral_constant<int, b>{}, cb0, cb1);
-                    if constexpr (ch == 0) run += ca0 + ca1;
-                } else {
-                    if constexpr (ch == 0) ca0 = ca1 = floatx16{};
-                    compute(std::integral_constant<int, b>{}, ca0, ca1);
-                    if constexpr (ch == 0) run += cb0 + cb1;
-                }
-            });
-        }
-        run += cb0 + cb1;   // the last displacement (TD is even)
-    }
-    if constexpr (NSPLIT > 1) {
-        __shared__ floatx16 red[NSPLIT - 1][TPW][64];
-        if (hs > 0) red[hs - 1][wv % TPW][lane] = run;
-        __syncthreads();
-        if (hs > 0) return;
-#pragma unroll
-        for (int h = 0; h < NSPLIT - 1; ++h) run += red[h][wv % TPW][lane];
-    }
-    if (!active) return;
-
-    // C[cell][node]: lane l, register r -> node j = l % 32, cell
-    // ii = 4 (l / 32) + (r % 4) + 8 (r / 4)
-    const int j = nb * 32 + (lane & 31);
-    if (j >= S::N3) return;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int ii = 4 * (lane >> 5) + (r & 3) + 8 * (r >> 2);
-        const int64_t P2 = Pm0 + ii;
-        if (P2 >= nparent) continue;
-        const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
-        const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
-        loc[c * NS + j] = inv_side * run[r];
-    }
-}
-
 // ------------------------------------------------- LDS-staged float kernel
 
 // 16 bytes per lane from global memory straight into LDS: lane l's bytes land
@@ -423,7 +224,7 @@ template <int CH> __device__ __forceinline__ int lds_rot(int q)
     else return q + (q >> 3);
 }
 
-// Same contraction as k_m2l_mx, with the operands staged through LDS.
+// The float and bf16 contraction, with the operands staged through LDS.
 //
 // A workgroup holds TPW = 4 / NSPLIT tiles of one (parity, node block) and
 // NSPLIT parts of the interaction list.  Per step every wave copies its
@@ -433,6 +234,11 @@ template <int CH> __device__ __forceinline__ int lds_rot(int q)
 // global memory to LDS into a ring of NST stages, NST - 1 steps ahead of the
 // products, so that reads that miss L2 are covered without holding them in
 // registers; one barrier per step publishes a stage and retires the oldest.
+//
+// Workgroups are numbered (tile group, parity, node block) with the node
+// block fastest, level by level, and the id is remapped so that each of the
+// 8 XCDs gets a contiguous range: a compact region of space whose targets of
+// all parities share their sources in that XCD's L2.
 template <int N, bool BF16, int CH, int NSPLIT, int NST>
 __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, const int *__restrict__ mxtab,
                                                  MxLevels lv, const float *__restrict__ phipad,
@@ -806,15 +612,6 @@ int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int
     return wgs;
 }
 
-// k-chunk per pipeline step (float4 loads of A and of B per lane): 4 for
-// n <= 4, where more resident waves pay off, 8 above (measured); NST
-// register stages, deep enough to cover reads that miss L2
-template <int N> struct MxChunk {
-    static constexpr int NA = MxShape<N>::KH / 4;
-    static constexpr int CH = N <= 4 ? (NA % 4 == 0 ? 4 : NA) : (NA % 8 == 0 ? 8 : (NA % 4 == 0 ? 4 : NA));
-    static constexpr int NST = N <= 4 ? 2 : 4;
-};
-
 // LDS-staged far field: 16-byte pieces per lane and step, ring depth
 template <int N> struct MxLds {
     static constexpr int NA = MxShape<N>::KH / 4;
@@ -850,9 +647,7 @@ template <int N>
 int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const float *phipad,
               float *loc, hipStream_t st)
 {
-    constexpr bool kLds = true;
     using S = MxShape<N>;
-    constexpr int CH = MxChunk<N>::CH;
     const Geom &g = plan->g;
     const int *tab = plan->ops.mxtab;
     // waves per tile: enough waves to keep every SIMD busy
@@ -870,16 +665,11 @@ int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const in
     auto go = [&](int l0, int l1, bool use_bf) -> int {
         if (l0 > l1) return EQFMM_OK;
         MxLevels lv;
-        const int nwg = kLds ? fill_levels_tg(g, l0, l1, lvl, plvl, S::NB, 4 / split, lv)
-                             : fill_levels(g, l0, l1, lvl, plvl, 32, S::NB, 4 / split, lv);
+        const int nwg = fill_levels_tg(g, l0, l1, lvl, plvl, S::NB, 4 / split, lv);
         const int grid = (nwg + 7) & ~7;
         const void *K = use_bf ? Kbf : plan->ops.Kmx;
-#define EQ_M2L_LAUNCH(B, SP)                                                                            \
-    if (kLds)                                                                                           \
-        k_m2l_lds<N, B, MxLds<N>::CH, SP, MxLds<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, \
-                                                                              nwg);                    \
-    else                                                                                                \
-        k_m2l_mx<N, B, CH, SP, MxChunk<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg)
+#define EQ_M2L_LAUNCH(B, SP)                                                                               \
+    k_m2l_lds<N, B, MxLds<N>::CH, SP, MxLds<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg)
 #define EQ_M2L_SPLIT(B)                          \
     if (split == 1) EQ_M2L_LAUNCH(B, 1);         \
     else if (split == 2) EQ_M2L_LAUNCH(B, 2);    \
