@@ -432,6 +432,11 @@ int scan(const int *in, int *out, int64_t len, int *blk, int clampv, int64_t *to
 
 // --------------------------------------------------------- a3: replacement
 
+// A workgroup owns CPB consecutive cells, whose charges are one contiguous
+// range.  The charges are taken a chunk of blockDim.x at a time: each thread
+// evaluates the Lagrange basis of one charge along the three axes into LDS,
+// then the thread of coefficient a = i + n j + n^2 k of a cell adds
+// q g_i(u) g_j(v) g_k(w) over the charges of its cell in the chunk.
 template <int N, typename R>
 __global__ void __launch_bounds__(512) k_p2m(const R *t_, const R *den_, int64_t nleaf,
                                              const int *leafstart, const double *su, const double *sv,
@@ -439,32 +444,48 @@ __global__ void __launch_bounds__(512) k_p2m(const R *t_, const R *den_, int64_t
 {
     using O = Ord<N>;
     constexpr int CPB = O::TPC >= 256 ? 1 : 256 / O::TPC;
+    constexpr int CHK = CPB * O::TPC;   // threads per workgroup = charges per chunk
+    __shared__ R gb[3][N][CHK];
+    __shared__ R qs[CHK];
     const int cl = threadIdx.x / O::TPC, a = threadIdx.x % O::TPC;
-    const int64_t c = int64_t(blockIdx.x) * CPB + cl;
-    if (c >= nleaf || a >= O::NS) return;
-    R acc = R(0);
-    if (a < O::N3) {
-        R t[N], den[N];
+    const int64_t cb = int64_t(blockIdx.x) * CPB;
+    const int64_t ce = cb + CPB < nleaf ? cb + CPB : nleaf;
+    const int64_t c = cb + cl;
+    const int P0 = leafstart[cb], P1 = leafstart[ce];
+    const bool mine = c < nleaf && a < O::N3;
+    const int p0 = mine ? leafstart[c] : 0, p1 = mine ? leafstart[c + 1] : 0;
+    R t[N], den[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            t[k] = t_[k];
-            den[k] = den_[k];
-        }
-        const int i = a % N, j = (a / N) % N, k = a / (N * N);
-        const int p0 = leafstart[c], p1 = leafstart[c + 1];
-        for (int p = p0; p < p1; ++p) {
-            R gx = den[i], gy = den[j], gz = den[k];
-            const R u = R(su[p]), v = R(sv[p]), w = R(sw[p]);
-#pragma unroll
-            for (int m = 0; m < N; ++m) {
-                if (m != i) gx *= u - t[m];
-                if (m != j) gy *= v - t[m];
-                if (m != k) gz *= w - t[m];
-            }
-            acc += sq[p] * gx * gy * gz;
-        }
+    for (int k = 0; k < N; ++k) {
+        t[k] = t_[k];
+        den[k] = den_[k];
     }
-    phiL[c * O::NS + a] = acc;
+    const int i = a % N, j = (a / N) % N, k = a / (N * N);
+    R acc = R(0);
+    for (int q0 = P0; q0 < P1; q0 += CHK) {
+        const int p = q0 + int(threadIdx.x);
+        if (p < P1) {
+            const R uvw[3] = {R(su[p]), R(sv[p]), R(sw[p])};
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    R g = den[b];
+#pragma unroll
+                    for (int m = 0; m < N; ++m)
+                        if (m != b) g *= uvw[ax] - t[m];
+                    gb[ax][b][threadIdx.x] = g;
+                }
+            qs[threadIdx.x] = sq[p];
+        }
+        __syncthreads();
+        if (mine) {
+            const int lo = (p0 > q0 ? p0 : q0) - q0, hi = (p1 < q0 + CHK ? p1 : q0 + CHK) - q0;
+            for (int e = lo; e < hi; ++e) acc += qs[e] * gb[0][i][e] * gb[1][j][e] * gb[2][k][e];
+        }
+        __syncthreads();
+    }
+    if (c < nleaf && a < O::NS) phiL[c * O::NS + a] = mine ? acc : R(0);
 }
 
 // -------------------------------------------------------- a4: shift upward
