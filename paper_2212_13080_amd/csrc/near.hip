@@ -91,7 +91,19 @@ __device__ __forceinline__ void l2p_part(const R *t_, const R *den_, const R *Lc
 }
 
 template <typename R> __device__ __forceinline__ R rsqrt_t(R x);
-template <> __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+// double: the hardware estimate refined by two Newton-Raphson steps for
+// y = x^(-1/2) (y <- y + y (1 - x y^2) / 2, each step squaring the relative
+// error), accurate to a few ulp for the positive normal r^2 of distinct charges
+template <> __device__ __forceinline__ double rsqrt_t<double>(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
 // the hardware reciprocal square root (1 ulp); r^2 of two distinct charges
 // is never a float denormal at the box scales in use
 template <> __device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
