@@ -30,6 +30,7 @@ namespace eqfmm {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 // The interaction levels of one evaluation, handled by a single launch:
 // workgroups [wg_begin[i], wg_begin[i+1]) belong to level level[i].
@@ -239,19 +240,42 @@ template <int CH> __device__ __forceinline__ int lds_rot(int q)
 // block fastest, level by level, and the id is remapped so that each of the
 // 8 XCDs gets a contiguous range: a compact region of space whose targets of
 // all parities share their sources in that XCD's L2.
-template <int N, bool BF16, int CH, int NSPLIT, int NST>
+// Element and tile shapes of the three forms: float and bf16 products use
+// v_mfma_f32_32x32x2f32 / v_mfma_f32_32x32x16_bf16 on 32 target cells x 32
+// nodes with the source axis in two halves; double uses v_mfma_f64_16x16x4f64
+// on 16 cells x 16 nodes with the source axis in four quarters.
+enum { MX_F32 = 0, MX_BF16 = 1, MX_F64 = 2 };
+template <int N, int MODE> struct MxForm {
+    static constexpr bool F64 = MODE == MX_F64, BF16 = MODE == MX_BF16;
+    using E = typename std::conditional<F64, double, float>::type;      // Phi, L
+    using BT = typename std::conditional<F64, double2,
+                                         typename std::conditional<BF16, bf16x8, float4>::type>::type;
+    using ACC = typename std::conditional<F64, doublex4, floatx16>::type;
+    static constexpr int N3 = N * N * N, NS = (N3 + 15) & ~15;
+    static constexpr int CELLS = F64 ? 16 : 32;     // target cells (parents) per tile
+    static constexpr int KG = F64 ? 4 : 2;          // source-axis groups (lane groups)
+    static constexpr int KP = NS / KG;              // sources per group
+    static constexpr int EPP = 16 / int(sizeof(E)); // elements per 16-byte piece
+    static constexpr int NA = KP / EPP;             // pieces per group of one row
+    static constexpr int NB = (N3 + CELLS - 1) / CELLS;   // node blocks
+    static constexpr int REGS = F64 ? 4 : 16;       // accumulator registers
+};
+
+template <int N, int MODE, int CH, int NSPLIT, int NST>
 __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, const int *__restrict__ mxtab,
-                                                 MxLevels lv, const float *__restrict__ phipad,
-                                                 float *__restrict__ loc_all, int nwg)
+                                                 MxLevels lv, const void *__restrict__ phipad_,
+                                                 void *__restrict__ loc_all_, int nwg)
 {
-    using S = MxShape<N>;
-    constexpr int NS = S::NS, KH = S::KH, NB = S::NB;
-    constexpr int NA = KH / 4;            // 16-byte pieces of one half row
+    using F = MxForm<N, MODE>;
+    using E = typename F::E;
+    using BT = typename F::BT;
+    using ACC = typename F::ACC;
+    constexpr bool BF16 = F::BF16, F64 = F::F64;
+    constexpr int NS = F::NS, KP = F::KP, NB = F::NB, NA = F::NA, CELLS = F::CELLS, EPP = F::EPP;
     constexpr int NCH = NA / CH;          // steps per displacement
     static_assert(NA % CH == 0 && (CH & (CH - 1)) == 0 && CH <= 8, "chunking");
     static_assert(!BF16 || CH % 2 == 0, "bf16 steps take 8 sources per lane");
     static_assert(NST >= 2, "ring depth");
-    using BT = typename std::conditional<BF16, bf16x8, float4>::type;
     constexpr int NBL = BF16 ? CH / 2 : CH;   // matrix pieces per lane and step
     constexpr int NBK = BF16 ? NA / 2 : NA;   // matrix pieces per lane, node block and displacement
     constexpr int TPW = 4 / NSPLIT;
@@ -260,6 +284,8 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     constexpr int AU = 64 * CH, BU = 64 * NBL, SU = 4 * AU + NSPLIT * BU;   // 16-byte units
     __shared__ float4 ring[NST * SU];
     __shared__ int stab[kListLen];
+    const E *phipad = static_cast<const E *>(phipad_);
+    E *loc_all = static_cast<E *>(loc_all_);
 
     const int per = gridDim.x >> 3;
     int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -268,8 +294,8 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     while (li + 1 < lv.nlev && wg >= lv.wg_begin[li + 1]) ++li;
     wg -= lv.wg_begin[li];
     const int level = lv.level[li], ntile = lv.ntile[li];
-    const float inv_side = lv.inv_side[li];
-    float *loc = loc_all + lv.cell0[li] * NS;
+    const E inv_side = F64 ? E(lv.inv_side64[li]) : E(lv.inv_side[li]);
+    E *loc = loc_all + lv.cell0[li] * NS;
     // workgroups (tile group, parity, node block), node block fastest
     const int nb = wg % NB, tp = wg / NB;
     const int p = tp & 7, tg = tp >> 3;
@@ -287,21 +313,23 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
     const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
     const int64_t nparent = int64_t(Dp) * Dp * Dp;
-    const int64_t Pm0 = int64_t(ta) * 32;
+    const int64_t Pm0 = int64_t(ta) * CELLS;
     const int x0 = 2 * compact3(Pm0) + px, y0 = 2 * compact3(Pm0 >> 1) + py, z0 = 2 * compact3(Pm0 >> 2) + pz;
-    const float *phi0 =
+    const E *phi0 =
         phipad + (lv.pcell0[li] + (int64_t(z0 + kHalo) * P + (y0 + kHalo)) * P + (x0 + kHalo)) * NS;
     // source-row copies: copy m, lane l fills unit u = 64 m + l of the wave's
-    // chunk, i.e. piece c of consumer lane q = u / CH (cell q % 32, half q / 32)
+    // chunk, i.e. piece c of consumer lane q = u / CH (cell q % CELLS,
+    // source group q / CELLS)
     uint32_t voffA[CH];
 #pragma unroll
     for (int m = 0; m < CH; ++m) {
         const int u = 64 * m + lane, q = u / CH;
         const int c = ((u % CH) - lds_rot<CH>(q)) & (CH - 1);
-        const int64_t Pq = Pm0 + (q & 31);
+        const int64_t Pq = Pm0 + (q % CELLS);
         const int64_t Pl = Pq < nparent ? Pq : Pm0;
         const int cx = 2 * compact3(Pl) + px, cy = 2 * compact3(Pl >> 1) + py, cz = 2 * compact3(Pl >> 2) + pz;
-        voffA[m] = uint32_t((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + (q >> 5) * KH + 4 * c) * 4u;
+        voffA[m] = uint32_t(((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + (q / CELLS) * KP + EPP * c) *
+                            int(sizeof(E)));
     }
     // LDS addresses (bytes) of the ring, and this lane's read offsets
     const uint32_t ring_lds = uint32_t(reinterpret_cast<uintptr_t>(ring));
@@ -319,7 +347,7 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
         const int e = __builtin_amdgcn_readfirstlane(stab[oidx]);
         const int oi = e & 511, delta = e >> 9;
         Copy cp;
-        cp.ab = reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS + ch * CH * 4);
+        cp.ab = reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS + ch * CH * EPP);
         cp.la = ring_lds + uint32_t((b * SU + wv * AU) * 16);
         cp.bb = kb + (size_t(oi) * NB * NBK + size_t(ch) * NBL) * 64 * sizeof(BT);
         cp.lb = ring_lds + uint32_t((b * SU + 4 * AU + hs * BU) * 16);
@@ -339,7 +367,7 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
         for (int k = 0; k < BPW; ++k) copy_b(cp, k);
     };
 
-    float4 abuf[2][CH];
+    float4 abuf[2][CH];   // 16-byte pieces (four floats or two doubles)
     BT bbuf[2][NBL];
     auto read = [&](auto bc, auto rc) {
         constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
@@ -355,12 +383,18 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
         }
     };
 
-    floatx16 ca0 = {}, ca1 = {}, cb0 = {}, cb1 = {}, run = {};
-    // the products of 16-byte piece c (float) or pair of pieces (bf16) of
-    // register set r into (x0, x1)
-    auto product = [&](auto rc, int c, floatx16 &x0, floatx16 &x1) {
+    ACC ca0 = {}, ca1 = {}, cb0 = {}, cb1 = {}, run = {};
+    // the products of 16-byte piece c (float, double) or pair of pieces
+    // (bf16) of register set r into (x0, x1)
+    auto product = [&](auto rc, int c, ACC &x0, ACC &x1) {
         constexpr int r = decltype(rc)::value;
-        if constexpr (!BF16) {
+        if constexpr (F64) {
+            double2 a, bv;
+            __builtin_memcpy(&a, &abuf[r][c], 16);
+            bv = bbuf[r][c];
+            x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bv.x, x0, 0, 0, 0);
+            x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bv.y, x1, 0, 0, 0);
+        } else if constexpr (!BF16) {
             const float4 a = abuf[r][c];
             const float4 bv = bbuf[r][c];
             x0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bv.x, x0, 0, 0, 0);
@@ -383,7 +417,6 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
         }
     };
     constexpr int NPR = BF16 ? NBL : CH;   // product groups per step
-
     // Trip of TS steps: a multiple of NST (ring stage), of 2 (register set)
     // and of 2 NCH (an even number of displacements, for the alternating
     // accumulator pairs), unrolled so that all three are constants.
@@ -413,8 +446,8 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
             // this step's products)
             read(std::integral_constant<int, (j + 1) % NST>{}, std::integral_constant<int, 1 - r>{});
             const Copy cp = setup(s + NST, std::integral_constant<int, b>{});
-            floatx16 &x0 = odd ? cb0 : ca0, &x1 = odd ? cb1 : ca1;
-            if constexpr (ch == 0) x0 = x1 = floatx16{};
+            ACC &x0 = odd ? cb0 : ca0, &x1 = odd ? cb1 : ca1;
+            if constexpr (ch == 0) x0 = x1 = ACC{};
             // products interleaved with the copies of step s + NST, in this
             // order (the matrix cores run while the copies are issued)
             static_for<0, NPR>([&](auto C) {
@@ -439,7 +472,7 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     wait_vmcnt<0>();
     wg_barrier();
     if constexpr (NSPLIT > 1) {
-        floatx16 *red = reinterpret_cast<floatx16 *>(ring);   // [NSPLIT - 1][TPW][64]
+        ACC *red = reinterpret_cast<ACC *>(ring);   // [NSPLIT - 1][TPW][64]
         if (hs > 0) red[((hs - 1) * TPW + tw) * 64 + lane] = run;
         __syncthreads();
         if (hs > 0) return;
@@ -448,120 +481,19 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     }
     if (!active) return;
 
-    // C[cell][node]: lane l, register r -> node j = l % 32, cell
-    // ii = 4 (l / 32) + (r % 4) + 8 (r / 4)
-    const int jn = nb * 32 + (lane & 31);
-    if (jn >= S::N3) return;
+    // C[cell][node]: float, lane l, register r -> node j = l % 32, cell
+    // ii = 4 (l / 32) + (r % 4) + 8 (r / 4); double, node j = l % 16, cell
+    // ii = l / 16 + 4 r
+    const int jn = nb * CELLS + (lane % CELLS);
+    if (jn >= F::N3) return;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int ii = 4 * (lane >> 5) + (r & 3) + 8 * (r >> 2);
+    for (int r = 0; r < F::REGS; ++r) {
+        const int ii = F64 ? (lane >> 4) + 4 * r : 4 * (lane >> 5) + (r & 3) + 8 * (r >> 2);
         const int64_t P2 = Pm0 + ii;
         if (P2 >= nparent) continue;
         const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
         const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
         loc[c * NS + jn] = inv_side * run[r];
-    }
-}
-
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
-// Double precision on the matrix cores (v_mfma_f64_16x16x4f64): a wave owns
-// 16 target cells of one parity (16 parents consecutive in Morton order, a
-// 4x2x2 block) and 16 target nodes; the source axis is split in four
-// quarters, one per quarter wave.  Same addressing and pipelining as the
-// float kernel.
-template <int N, int CH>
-__global__ void __launch_bounds__(256) k_m2l_f64(const double2 *__restrict__ Kmx, const int *__restrict__ mxtab,
-                                                 MxLevels lv, const double *__restrict__ phipad,
-                                                 double *__restrict__ loc_all, int nwg)
-{
-    constexpr int N3 = N * N * N, NS = (N3 + 15) & ~15, KQ = NS / 4, NB = (N3 + 15) / 16;
-    constexpr int NA = KQ / 2;            // double2 loads of one quarter row
-    constexpr int NCH = NA / CH;
-    static_assert(NA % CH == 0, "chunking");
-    const int per = gridDim.x >> 3;
-    int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (wg >= nwg) return;
-    int li = 0;
-    while (li + 1 < lv.nlev && wg >= lv.wg_begin[li + 1]) ++li;
-    wg -= lv.wg_begin[li];
-    const int level = lv.level[li], ntile = lv.ntile[li];
-    const double inv_side = lv.inv_side64[li];
-    double *loc = loc_all + lv.cell0[li] * NS;
-    // 4 work items (tile, parity, node block) per workgroup, node block fastest
-    const int nitem = ntile * 8 * NB;
-    const int lane = threadIdx.x & 63;
-    const int it = wg * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tp = it / NB, nb = it - tp * NB;
-    const int t = tp >> 3, p = tp & 7;
-    __shared__ int stab[8 * kListLen];
-    for (int k = threadIdx.x; k < 8 * kListLen; k += 256) stab[k] = mxtab[level * 8 * kListLen + k];
-    __syncthreads();
-    if (it >= nitem) return;
-    const int *ptab = stab + p * kListLen;
-    const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
-    const int D = 1 << level, Dp = D >> 1, P = D + 2 * kHalo;
-    const int64_t nparent = int64_t(Dp) * Dp * Dp;
-    const int i = lane & 15, gq = lane >> 4;
-    const int64_t Pm0 = int64_t(t) * 16, Pm = Pm0 + i;
-    const int64_t Pl = Pm < nparent ? Pm : Pm0;
-    const int x0 = 2 * compact3(Pm0) + px, y0 = 2 * compact3(Pm0 >> 1) + py, z0 = 2 * compact3(Pm0 >> 2) + pz;
-    const int cx = 2 * compact3(Pl) + px, cy = 2 * compact3(Pl >> 1) + py, cz = 2 * compact3(Pl >> 2) + pz;
-    const double *phi0 =
-        phipad + (lv.pcell0[li] + (int64_t(z0 + kHalo) * P + (y0 + kHalo)) * P + (x0 + kHalo)) * NS;
-    const uint32_t voff = uint32_t((((cz - z0) * P + (cy - y0)) * P + (cx - x0)) * NS + gq * KQ) * 8u;
-    const double2 *kb = Kmx + size_t(nb) * NA * 64 + lane;
-    double2 abuf[2][CH], bbuf[2][CH];
-
-    auto issue = [&](int step, auto bc) {
-        constexpr int b = decltype(bc)::value;
-        constexpr int nsteps = kListLen * NCH;
-        step = step < nsteps ? step : nsteps - 1;
-        const int oidx = step / NCH, ch = step - oidx * NCH;
-        const int e = __builtin_amdgcn_readfirstlane(ptab[oidx]);
-        const int oi = e & 511, delta = e >> 9;
-        const double2 *ap =
-            reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(phi0 + int64_t(delta) * NS) + voff) +
-            ch * CH;
-#pragma unroll
-        for (int c = 0; c < CH; ++c) abuf[b][c] = ap[c];
-        const double2 *bp = kb + (size_t(oi) * NB * NA + ch * CH) * 64;
-#pragma unroll
-        for (int c = 0; c < CH; ++c) bbuf[b][c] = bp[c * 64];
-    };
-
-    doublex4 c0 = {}, c1 = {}, run = {};
-    issue(0, std::integral_constant<int, 0>{});
-    for (int op = 0; op < kListLen; op += 2) {
-        static_for<0, 2 * NCH>([&](auto J) {
-            constexpr int j = decltype(J)::value;
-            constexpr int b = j & 1;
-            constexpr int ch = j % NCH;
-            issue(op * NCH + j + 1, std::integral_constant<int, 1 - b>{});
-            __builtin_amdgcn_sched_barrier(0);
-            if constexpr (ch == 0) {
-                c0 = doublex4{};
-                c1 = doublex4{};
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[b][c].x, bbuf[b][c].x, c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[b][c].y, bbuf[b][c].y, c1, 0, 0, 0);
-            }
-            if constexpr (ch == NCH - 1) run += c0 + c1;
-        });
-    }
-    // lane l, register r -> node j = l % 16, cell ii = l / 16 + 4 r
-    const int j = nb * 16 + (lane & 15);
-    if (j >= N3) return;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int ii = (lane >> 4) + 4 * r;
-        const int64_t P2 = Pm0 + ii;
-        if (P2 >= nparent) continue;
-        const int x = 2 * compact3(P2) + px, y = 2 * compact3(P2 >> 1) + py, z = 2 * compact3(P2 >> 2) + pz;
-        const int64_t c = x + int64_t(D) * (y + int64_t(D) * z);
-        loc[c * NS + j] = inv_side * run[r];
     }
 }
 
@@ -588,41 +520,17 @@ double il_pairs(const Geom &g, int level)
     return double(A) * A * A - double(B) * B * B;
 }
 
-// Level table: tiles of `cells_per_tile` parents, 8 parities and `nb` node
-// blocks per tile, `tpw` (tile, parity, node block) items per workgroup.
-int fill_levels(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int cells_per_tile,
-                int nb, int tpw, MxLevels &lv)
-{
-    lv.nlev = lmax - lmin + 1;
-    int wgs = 0;
-    for (int i = 0; i < lv.nlev; ++i) {
-        const int l = lmin + i;
-        const int Dp = (1 << l) >> 1;
-        const int64_t nparent = int64_t(Dp) * Dp * Dp;
-        lv.level[i] = l;
-        lv.ntile[i] = int((nparent + cells_per_tile - 1) / cells_per_tile);
-        lv.wg_begin[i] = wgs;
-        wgs += (lv.ntile[i] * 8 * nb + tpw - 1) / tpw;
-        lv.cell0[i] = lvl[l];
-        lv.pcell0[i] = plvl[l];
-        lv.inv_side[i] = float(double(1 << l) / g.box);
-        lv.inv_side64[i] = double(1 << l) / g.box;
-    }
-    lv.wg_begin[lv.nlev] = wgs;
-    return wgs;
-}
-
-// LDS-staged far field: 16-byte pieces per lane and step, ring depth
-template <int N> struct MxLds {
-    static constexpr int NA = MxShape<N>::KH / 4;
+// LDS-staged far field: CH 16-byte pieces per lane and step, NST ring stages
+template <int N, int MODE> struct MxLds {
+    static constexpr int NA = MxForm<N, MODE>::NA;
     static constexpr int CH = NA % 4 == 0 ? 4 : 2;
     static constexpr int NST = 3;
 };
 
 // Level table of the LDS-staged kernel: one workgroup per (group of tpw
-// tiles, parity, node block).
-int fill_levels_tg(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int nb, int tpw,
-                   MxLevels &lv)
+// tiles of `cells` parents, parity, node block).
+int fill_levels_tg(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int cells, int nb,
+                   int tpw, MxLevels &lv)
 {
     lv.nlev = lmax - lmin + 1;
     int wgs = 0;
@@ -631,7 +539,7 @@ int fill_levels_tg(const Geom &g, int lmin, int lmax, const int64_t *lvl, const 
         const int Dp = (1 << l) >> 1;
         const int64_t nparent = int64_t(Dp) * Dp * Dp;
         lv.level[i] = l;
-        lv.ntile[i] = int((nparent + 31) / 32);
+        lv.ntile[i] = int((nparent + cells - 1) / cells);
         lv.wg_begin[i] = wgs;
         wgs += (lv.ntile[i] + tpw - 1) / tpw * 8 * nb;
         lv.cell0[i] = lvl[l];
@@ -643,63 +551,56 @@ int fill_levels_tg(const Geom &g, int lmin, int lmax, const int64_t *lvl, const 
     return wgs;
 }
 
+// The far-field products of levels [l0, l1] in one launch of form MODE.
+template <int N, int MODE>
+int launch_lds(eqfmm_plan *plan, int l0, int l1, const int64_t *lvl, const int64_t *plvl, const void *K,
+               const void *phipad, void *loc, hipStream_t st)
+{
+    using F = MxForm<N, MODE>;
+    using C = MxLds<N, MODE>;
+    const Geom &g = plan->g;
+    // waves per tile: enough waves to keep every SIMD busy
+    int64_t tiles = 0;
+    for (int l = l0; l <= l1; ++l) {
+        const int64_t Dp = (int64_t(1) << l) >> 1;
+        tiles += 8 * F::NB * ((Dp * Dp * Dp + F::CELLS - 1) / F::CELLS);
+    }
+    const int split = tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4);
+    MxLevels lv;
+    const int nwg = fill_levels_tg(g, l0, l1, lvl, plvl, F::CELLS, F::NB, 4 / split, lv);
+    const int grid = (nwg + 7) & ~7;
+    const int *tab = plan->ops.mxtab;
+    if (split == 1)
+        k_m2l_lds<N, MODE, C::CH, 1, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg);
+    else if (split == 2)
+        k_m2l_lds<N, MODE, C::CH, 2, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg);
+    else
+        k_m2l_lds<N, MODE, C::CH, 4, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg);
+    return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+}
+
 template <int N>
 int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const float *phipad,
               float *loc, hipStream_t st)
 {
-    using S = MxShape<N>;
     const Geom &g = plan->g;
-    const int *tab = plan->ops.mxtab;
-    // waves per tile: enough waves to keep every SIMD busy
-    int64_t tiles = 0;
-    for (int l = lmin; l <= lmax; ++l) {
-        const int64_t Dp = (int64_t(1) << l) >> 1;
-        tiles += 8 * S::NB * ((Dp * Dp * Dp + 31) / 32);
-    }
-    const int split = tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4);
     // bf16 inputs only on the two finest levels, which carry nearly all the
     // work; on coarse levels the cells hold many charges and bf16 rounding of
     // their large, sign-cancelling vectors leaves a spurious net charge
     const bool bf = plan->p.precision == EQFMM_FP32_BF16FAR;
     const void *Kbf = static_cast<const unsigned char *>(plan->ops.Kmx) + mx_f32_bytes(g);
-    auto go = [&](int l0, int l1, bool use_bf) -> int {
-        if (l0 > l1) return EQFMM_OK;
-        MxLevels lv;
-        const int nwg = fill_levels_tg(g, l0, l1, lvl, plvl, S::NB, 4 / split, lv);
-        const int grid = (nwg + 7) & ~7;
-        const void *K = use_bf ? Kbf : plan->ops.Kmx;
-#define EQ_M2L_LAUNCH(B, SP)                                                                               \
-    k_m2l_lds<N, B, MxLds<N>::CH, SP, MxLds<N>::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg)
-#define EQ_M2L_SPLIT(B)                          \
-    if (split == 1) EQ_M2L_LAUNCH(B, 1);         \
-    else if (split == 2) EQ_M2L_LAUNCH(B, 2);    \
-    else EQ_M2L_LAUNCH(B, 4);
-        if (use_bf) { EQ_M2L_SPLIT(true) }
-        else { EQ_M2L_SPLIT(false) }
-#undef EQ_M2L_SPLIT
-#undef EQ_M2L_LAUNCH
-        return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
-    };
-    if (!bf) return go(lmin, lmax, false);
+    if (!bf) return launch_lds<N, MX_F32>(plan, lmin, lmax, lvl, plvl, plan->ops.Kmx, phipad, loc, st);
     const int lb = lmax - 1 > lmin ? lmax - 1 : lmin;
-    const int rc = go(lmin, lb - 1, false);
-    return rc ? rc : go(lb, lmax, true);
+    int rc = EQFMM_OK;
+    if (lmin <= lb - 1) rc = launch_lds<N, MX_F32>(plan, lmin, lb - 1, lvl, plvl, plan->ops.Kmx, phipad, loc, st);
+    return rc ? rc : launch_lds<N, MX_BF16>(plan, lb, lmax, lvl, plvl, Kbf, phipad, loc, st);
 }
 
 template <int N>
 int launch_f64(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl,
                const double *phipad, double *loc, hipStream_t st)
 {
-    constexpr int NA = ((N * N * N + 15) & ~15) / 8;
-    constexpr int CH = NA % 4 == 0 ? 4 : (NA % 2 == 0 ? 2 : 1);
-    constexpr int NB = (N * N * N + 15) / 16;
-    const Geom &g = plan->g;
-    MxLevels lv;
-    const int nwg = fill_levels(g, lmin, lmax, lvl, plvl, 16, NB, 4, lv);
-    const int grid = (nwg + 7) & ~7;
-    const double2 *K = static_cast<const double2 *>(plan->ops.Kmx);
-    k_m2l_f64<N, CH><<<grid, 256, 0, st>>>(K, plan->ops.mxtab, lv, phipad, loc, nwg);
-    return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
+    return launch_lds<N, MX_F64>(plan, lmin, lmax, lvl, plvl, plan->ops.Kmx, phipad, loc, st);
 }
 
 template <typename R, int N>
