@@ -1,0 +1,103 @@
+"""Full-size checks of the larger workloads (c3-c5), in the configuration
+bench.py times.  At these sizes the oracle's whole evaluation is too slow for
+a test, so the checks are properties that hold at any size:
+
+* the symmetries of the octree: a sign flip of every charge, the reflection
+  x -> 1 - x and a cyclic swap of the axes each map every level's cells, basis
+  nodes and interaction lists onto themselves, so the method's result
+  transforms exactly, up to rounding (FP64 within 1e-10, FP32 within 1e-5 of
+  the transformed FP64 result);
+* E = 1/2 sum q phi, dE/dq = phi and dE/dx = -q E_field (Sec. 2, Eq. 15);
+* FP32 against FP64 within 1e-5 relative RMS (the accuracy bar of the FP32
+  path; the FP64 path itself is held to 1e-10 of the oracle at the sizes the
+  oracle finishes and on the full 262144-charge free-space workload).
+
+A shift of the charges by one finest cell is not among them: the coarser
+levels then group the charges differently, and the result moves by the
+method's truncation error, not by rounding."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+os.makedirs("gpurun_out", exist_ok=True)
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2212_13080_amd as eq  # noqa: E402
+import workloads  # noqa: E402
+from gpu_common import rel_rms  # noqa: E402
+
+
+def evaluate(plan, pos, q):
+    pt, qt = torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda()
+    E, phi, field = plan.forward(pt, qt)
+    dx, dq = plan.backward(qt, torch.ones((), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    return dict(energy=E.item(), phi=phi.double().cpu().numpy(), field=field.double().cpu().numpy(),
+                dEdx=dx.double().cpu().numpy(), dEdq=dq.double().cpu().numpy())
+
+
+def mirror_x(pos, levels):
+    """x -> 1 - x.  A charge at x = 0 goes to the largest double below 1
+    (the point 1 itself lies outside [0, 1)); the test asserts that every
+    charge lands in the mirror leaf, so the octree maps onto itself."""
+    m = pos.copy()
+    m[:, 0] = 1.0 - pos[:, 0]
+    m[m[:, 0] >= 1.0, 0] = np.nextafter(1.0, 0.0)
+    side = 1 << levels
+    assert np.array_equal(np.floor(m[:, 0] * side), side - 1 - np.floor(pos[:, 0] * side))
+    return m
+
+
+# (name, positions, charges, phi back, field back): the last two map the
+# transformed run's outputs onto the untransformed charges' outputs.
+TRANSFORMS = [
+    ("sign flip", lambda p, q, L: (p, -q), lambda f: -f, lambda e: -e),
+    ("reflection x->1-x", lambda p, q, L: (mirror_x(p, L), q), lambda f: f, lambda e: e * np.array([-1.0, 1.0, 1.0])),
+    ("axis cycle", lambda p, q, L: (np.ascontiguousarray(p[:, [1, 2, 0]]), q), lambda f: f,
+     lambda e: np.ascontiguousarray(e[:, [2, 0, 1]])),
+]
+
+
+def check_adjoint(g, q, scale, tol):
+    assert abs(g["energy"] - 0.5 * np.dot(q, g["phi"])) <= tol * scale
+    assert rel_rms(g["dEdq"], g["phi"]) <= tol
+    assert rel_rms(g["dEdx"], -q[:, None] * g["field"]) <= tol
+
+
+@pytest.mark.parametrize("key", ["c3", "c4", "c5"])
+def test_full_size_properties(key):
+    w, pos, q = workloads.workload_inputs(key)
+    print(f"case {w.name} N={w.n} f64", flush=True)
+    p64 = eq.Plan(w.levels, w.order, w.boundary, eq.FP64)
+    r = evaluate(p64, pos, q)
+    scale = 0.5 * np.abs(q * r["phi"]).sum()
+    check_adjoint(r, q, scale, 1e-12)
+    lines = []
+    for name, fwd, back_phi, back_field in TRANSFORMS:
+        tp, tq = fwd(pos, q, w.levels)
+        print(f"case {w.name} f64 {name}", flush=True)
+        t = evaluate(p64, tp, tq)
+        err = (rel_rms(back_phi(t["phi"]), r["phi"]), rel_rms(back_field(t["field"]), r["field"]))
+        lines.append(f"f64 {name}: phi {err[0]:.2e} field {err[1]:.2e}")
+        print("  " + lines[-1], flush=True)
+        assert max(err) <= 1e-10
+        assert abs(t["energy"] - r["energy"]) <= 1e-10 * scale
+    del p64
+    p32 = eq.Plan(w.levels, w.order, w.boundary, eq.FP32)
+    for name, fwd, back_phi, back_field in [("identity", lambda p, q, L: (p, q), lambda f: f, lambda e: e)] + TRANSFORMS:
+        tp, tq = fwd(pos, q, w.levels)
+        print(f"case {w.name} f32 {name}", flush=True)
+        g = evaluate(p32, tp, tq)
+        check_adjoint(g, tq, scale, 1e-6)
+        err = (rel_rms(back_phi(g["phi"]), r["phi"]), rel_rms(back_field(g["field"]), r["field"]))
+        lines.append(f"f32 {name} vs f64: phi {err[0]:.2e} field {err[1]:.2e}")
+        print("  " + lines[-1], flush=True)
+        assert max(err) <= 1e-5
+        assert abs(g["energy"] - r["energy"]) <= 1e-5 * scale
+    with open(f"gpurun_out/full_size_{key}.txt", "w") as fh:
+        fh.write(w.name + "\n" + "\n".join(lines) + "\n")
