@@ -148,8 +148,11 @@ int eqfmm_plan_destroy(eqfmm_plan *plan);
 
 const char *eqfmm_strerror(int code);
 
-/* Stage timing with HIP events recorded on the work stream.  While enabled,
- * every launch of a stage is bracketed by events; eqfmm_profile_read
+/* Stage timing with HIP events recorded on the stream each stage runs on.
+ * `stages` is a bit mask (bit s times stage s, EQFMM_STAGES_ALL every stage,
+ * 0 none); every launch of a timed stage is bracketed by two events, which
+ * costs a few microseconds per pair, so a throughput measurement should time
+ * only the stages it reports.  eqfmm_profile_read
  * synchronises and returns, for `stage` (EQFMM_STAGE_*), the summed kernel
  * time in ms, the number of launches, and the algorithmic flop and byte
  * counts of those launches (EQFMM_STAGE_M2L: one launch covers every
@@ -157,9 +160,9 @@ const char *eqfmm_strerror(int code);
 enum {
     EQFMM_STAGE_BIN = 0, EQFMM_STAGE_P2M = 1, EQFMM_STAGE_M2M = 2, EQFMM_STAGE_M2L = 3,
     EQFMM_STAGE_L2L = 4, EQFMM_STAGE_LEAF = 5, EQFMM_STAGE_GATHER = 6, EQFMM_STAGE_ADJOINT = 7,
-    EQFMM_NUM_STAGES = 8
+    EQFMM_NUM_STAGES = 8, EQFMM_STAGES_ALL = (1 << 8) - 1
 };
-int eqfmm_profile_enable(eqfmm_plan *plan, int enable);
+int eqfmm_profile_enable(eqfmm_plan *plan, int stages);
 int eqfmm_profile_read(eqfmm_plan *plan, int stage, double *ms, int64_t *launches,
                        double *flops, double *bytes);
 

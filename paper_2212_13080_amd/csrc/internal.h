@@ -49,7 +49,7 @@ struct HostOps {
 };
 
 struct Profile {
-    int enabled = 0;
+    unsigned mask = 0;                // bit s: stage s is timed
     std::vector<hipEvent_t> pool;
     std::vector<int> stage_of;        // per event pair
     std::vector<double> flops_of, bytes_of;

@@ -26,14 +26,16 @@ namespace eqfmm {
 
 namespace {
 
-int prof_begin(eqfmm_plan *plan, hipStream_t st)
+int prof_begin(eqfmm_plan *plan, hipStream_t st, int stage)
 {
     Profile &P = plan->prof;
-    if (!P.enabled) return -1;
+    if (!((P.mask >> stage) & 1u)) return -1;
     const size_t k = P.stage_of.size();
     while (P.pool.size() < 2 * (k + 1)) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        // timing only: no system-scope fence, which would write back and
+        // invalidate the caches under the kernels that follow
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
         P.pool.push_back(e);
     }
     if (hipEventRecord(P.pool[2 * k], st) != hipSuccess) return -1;
@@ -778,7 +780,7 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     const size_t rs = sizeof(R);
 
     // a1/a2: validate, split, count per cell, prefix sums
-    int pk = prof_begin(plan, st);
+    int pk = prof_begin(plan, st, EQFMM_STAGE_BIN);
     k_clear<<<blocks(nleaf + 1, 256), 256, 0, st>>>(v.hdr, v.leafcnt, v.cursor, nleaf);
     k_count<N><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, n, pos, q, v.cnt, v.fstart, v.smask, v.leafcnt,
                                                  v.hdr);
@@ -804,7 +806,7 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     if (!sd) return EQFMM_ESTATE;
     EQ_CHECK(hipEventRecord(plan->ev_bin, st));
     EQ_CHECK(hipStreamWaitEvent(sd, plan->ev_bin, 0));
-    pk = prof_begin(plan, sd);
+    pk = prof_begin(plan, sd, EQFMM_STAGE_LEAF);
     rc = launch_p2p<R>(plan, n, W.fcap, v.leafstart, v.su, v.sv, v.sw, v.sq, v.spar, v.sleaf, v.smask, v.sphi,
                        v.snf, sd);
     if (rc) return rc;
@@ -813,7 +815,7 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
 
     // a3: replacement at the finest cells
     const int L = g.L;
-    pk = prof_begin(plan, st);
+    pk = prof_begin(plan, st, EQFMM_STAGE_P2M);
     {
         constexpr int CPB = O::TPC >= 256 ? 1 : 256 / O::TPC;
         const int tpb = CPB * O::TPC;
@@ -826,7 +828,7 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
 
     // a4: upward pass; free space needs Phi down to level 2, periodic to 0
     const int lmin = g.periodic ? 1 : 2;
-    pk = prof_begin(plan, st);
+    pk = prof_begin(plan, st, EQFMM_STAGE_M2M);
     for (int l = L; l > (g.periodic ? 0 : 2); --l) {
         const int Dl = 1 << l;
         const int64_t np = int64_t(1) << (3 * (l - 1));
@@ -851,7 +853,7 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     if (rc) return rc;
     // free space: Psi vanishes at levels 0 and 1, so the shifts start at 2 -> 3
     for (int l = g.periodic ? 1 : 3; l <= L; ++l) {
-        pk = prof_begin(plan, st);
+        pk = prof_begin(plan, st, EQFMM_STAGE_L2L);
         const int64_t np = int64_t(1) << (3 * (l - 1));
         k_l2l<N, R><<<dim3(unsigned(np)), O::TPC, 0, st>>>(G, 1 << l, v.loc + W.lvl[l - 1] * O::NS,
                                                            v.loc + W.lvl[l] * O::NS);
@@ -861,14 +863,14 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
 
     // a7: far field at the fragments, added to the near-field sums
     EQ_CHECK(hipStreamWaitEvent(st, plan->ev_near, 0));
-    pk = prof_begin(plan, st);
+    pk = prof_begin(plan, st, EQFMM_STAGE_LEAF);
     rc = launch_l2p<N, R>(plan, W.fcap, v.leafstart, t, den, v.su, v.sv, v.sw, v.spar, v.sleaf, v.smask,
                           v.loc + W.lvl[L] * O::NS, v.sphi, v.snf, v.sfld, st);
     if (rc) return rc;
     prof_end(plan, st, pk, EQFMM_STAGE_LEAF, 0.0, 0.0);
 
     // a9/a10: back to the charges, energy
-    pk = prof_begin(plan, st);
+    pk = prof_begin(plan, st, EQFMM_STAGE_GATHER);
     k_gather<R><<<dim3(unsigned(W.e_blocks)), 256, 0, st>>>(n, q, v.fstart, v.smask, v.gslot, v.gw,
                                                             v.gdw, v.sphi, v.sfld,
                                                             static_cast<R *>(phi_out),
@@ -884,7 +886,7 @@ int backward_impl(eqfmm_plan *plan, int64_t n, const double *q, const double *gE
                   void *dEdq, unsigned char *ws, const WsLayout &W, hipStream_t st)
 {
     Ws<R> v = views<R>(ws, W);
-    const int pk = prof_begin(plan, st);
+    const int pk = prof_begin(plan, st, EQFMM_STAGE_ADJOINT);
     if (n > 0) {
         k_adjoint<R><<<blocks(n, 256), 256, 0, st>>>(n, q, gE, v.fstart, v.smask, v.gslot, v.gw, v.gdw,
                                                      v.sphi, v.sfld, static_cast<R *>(dEdx),
@@ -929,7 +931,7 @@ int run_backward(eqfmm_plan *plan, int64_t n, const double *q, const double *gE,
 }
 
 // timing hooks for the far-field launcher (m2l.hip)
-int prof_begin_m2l(eqfmm_plan *plan, hipStream_t st) { return prof_begin(plan, st); }
+int prof_begin_m2l(eqfmm_plan *plan, hipStream_t st) { return prof_begin(plan, st, EQFMM_STAGE_M2L); }
 void prof_end_m2l(eqfmm_plan *plan, hipStream_t st, int k, double flops, double bytes)
 {
     prof_end(plan, st, k, EQFMM_STAGE_M2L, flops, bytes);

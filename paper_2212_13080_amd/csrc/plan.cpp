@@ -455,11 +455,11 @@ int eqfmm_plan_destroy(eqfmm_plan *plan)
     return EQFMM_OK;
 }
 
-int eqfmm_profile_enable(eqfmm_plan *plan, int enable)
+int eqfmm_profile_enable(eqfmm_plan *plan, int stages)
 {
     if (!plan) return EQFMM_EINVAL;
     Profile &P = plan->prof;
-    P.enabled = enable ? 1 : 0;
+    P.mask = unsigned(stages) & ((1u << EQFMM_NUM_STAGES) - 1u);
     P.used = 0;
     P.stage_of.clear();
     P.flops_of.clear();

@@ -108,8 +108,19 @@ class Plan:
         return dx, dq
 
     # profiling ------------------------------------------------------------
-    def profile(self, enable=True):
-        native.eqfmm_profile_enable(self.handle, enable)
+    def profile(self, stages=True):
+        """Time stages with HIP events: True for every stage, False for none,
+        or an iterable of stage names (native.STAGES).  Each timed launch
+        costs an event pair, so time only the stages that are read."""
+        if stages is True:
+            mask = (1 << len(native.STAGES)) - 1
+        elif not stages:
+            mask = 0
+        else:
+            mask = 0
+            for s in stages:
+                mask |= 1 << native.STAGES.index(s)
+        native.eqfmm_profile_enable(self.handle, mask)
 
     def profile_read(self):
         return {name: native.eqfmm_profile_read(self.handle, i) for i, name in enumerate(native.STAGES)}

@@ -125,8 +125,8 @@ def eqfmm_plan_destroy(plan):
     check(lib().eqfmm_plan_destroy(plan), "eqfmm_plan_destroy")
 
 
-def eqfmm_profile_enable(plan, enable: bool):
-    check(lib().eqfmm_profile_enable(plan, int(enable)), "eqfmm_profile_enable")
+def eqfmm_profile_enable(plan, stages: int):
+    check(lib().eqfmm_profile_enable(plan, int(stages)), "eqfmm_profile_enable")
 
 
 def eqfmm_profile_read(plan, stage: int):
