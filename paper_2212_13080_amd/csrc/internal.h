@@ -65,7 +65,7 @@ struct WsLayout {
     size_t hdr, cnt, fstart, smask, leafcnt, leafstart, cursor, scanblk;
     size_t su, sv, sw, sq, spar, sleaf;
     size_t gslot, gw, gdw;
-    size_t phi, phipad, loc, sphi, snf, sfld, epart;
+    size_t phi, phipad, loc, loc2, sphi, snf, sfld, epart;
     size_t total;
     int64_t scan_blocks, e_blocks;
     std::vector<int64_t> lvl;     // first cell of each level in the Phi / L arrays

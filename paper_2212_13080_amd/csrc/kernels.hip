@@ -548,7 +548,8 @@ __global__ void __launch_bounds__(Ord<N>::TPC) k_m2m(const R *G, int Dl, const R
 // ------------------------------------------------------ a6: shift downward
 
 template <int N, typename R>
-__global__ void __launch_bounds__(Ord<N>::TPC) k_l2l(const R *G, int Dl, const R *locp, R *locc)
+__global__ void __launch_bounds__(Ord<N>::TPC) k_l2l(const R *G, int Dl, const R *locp, const R *locp2, R *locc,
+                                                     const R *locc2)
 {
     using O = Ord<N>;
     constexpr int N3 = O::N3;
@@ -556,7 +557,9 @@ __global__ void __launch_bounds__(Ord<N>::TPC) k_l2l(const R *G, int Dl, const R
     const int Dp = Dl >> 1;
     const int64_t P = blockIdx.x;
     const int X = int(P % Dp), Y = int((P / Dp) % Dp), Z = int(P / (int64_t(Dp) * Dp));
-    for (int e = threadIdx.x; e < N3; e += blockDim.x) lp[e] = locp[P * O::NS + e];
+    // locp2 / locc2 (may be null): second halves of the far field
+    for (int e = threadIdx.x; e < N3; e += blockDim.x)
+        lp[e] = locp2 ? locp[P * O::NS + e] + locp2[P * O::NS + e] : locp[P * O::NS + e];
     for (int e = threadIdx.x; e < 2 * N * N; e += blockDim.x) Gs[e] = G[e];
     __syncthreads();
     // Psi_child(v) = Psi_parent(shift(v)): L_child = (G_bx x G_by x G_bz)^T L_parent
@@ -588,7 +591,8 @@ __global__ void __launch_bounds__(Ord<N>::TPC) k_l2l(const R *G, int Dl, const R
         for (int j3 = 0; j3 < N; ++j3)
             acc += Gs[(bz * N + j3) * N + i3] * uy[(bx + 2 * by) * N3 + i1 + N * i2 + N * N * j3];
         const int64_t c = (2 * X + bx) + int64_t(Dl) * ((2 * Y + by) + int64_t(Dl) * (2 * Z + bz));
-        locc[c * O::NS + e] += acc;
+        const R own = locc2 ? locc[c * O::NS + e] + locc2[c * O::NS + e] : locc[c * O::NS + e];
+        locc[c * O::NS + e] = own + acc;
     }
 }
 
@@ -708,7 +712,7 @@ template <typename R> struct Ws {
     WsHeader *hdr;
     int *cnt, *fstart, *leafcnt, *leafstart, *cursor, *scanblk, *spar, *sleaf, *gslot;
     unsigned char *smask;
-    R *sq, *phi, *phipad, *loc, *sfld;
+    R *sq, *phi, *phipad, *loc, *loc2, *sfld;
     double *su, *sv, *sw, *gw, *gdw, *sphi, *snf, *epart;
 };
 
@@ -735,6 +739,7 @@ template <typename R> Ws<R> views(unsigned char *b, const WsLayout &W)
     v.phi = reinterpret_cast<R *>(b + W.phi);
     v.phipad = reinterpret_cast<R *>(b + W.phipad);
     v.loc = reinterpret_cast<R *>(b + W.loc);
+    v.loc2 = reinterpret_cast<R *>(b + W.loc2);
     v.sphi = reinterpret_cast<double *>(b + W.sphi);
     v.snf = reinterpret_cast<double *>(b + W.snf);
     v.sfld = reinterpret_cast<R *>(b + W.sfld);
@@ -764,7 +769,9 @@ int launch_m2l_pad(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, con
                    R *phipad, hipStream_t st);
 template <typename R>
 int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const R *phipad,
-               R *loc, hipStream_t st);
+               R *loc, R *loc2, hipStream_t st);
+// levels (bit l) whose local vectors the far field leaves in two halves
+unsigned m2l_half_levels(const eqfmm_plan *plan);
 
 template <int N, typename R>
 int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q, void *phi_out,
@@ -849,14 +856,21 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
         k_root<R><<<1, 256, 0, st>>>(static_cast<const R *>(ops.T), O::N3, R(1.0 / g.box), v.phi, v.loc);
         EQ_CHECK(hipGetLastError());
     }
-    rc = launch_m2l<R>(plan, lmin, L, W.lvl.data(), W.plvl.data(), v.phipad, v.loc, st);
+    rc = launch_m2l<R>(plan, lmin, L, W.lvl.data(), W.plvl.data(), v.phipad, v.loc, v.loc2, st);
     if (rc) return rc;
-    // free space: Psi vanishes at levels 0 and 1, so the shifts start at 2 -> 3
-    for (int l = g.periodic ? 1 : 3; l <= L; ++l) {
+    // free space: Psi vanishes at levels 0 and 1, so the shifts start at 2 -> 3.
+    // A level whose far field came in two halves gets the second half added
+    // as it receives its parent's functional (the top level, a parent only,
+    // as it gives it).
+    const unsigned hm = m2l_half_levels(plan);
+    const int l0 = g.periodic ? 1 : 3;
+    for (int l = l0; l <= L; ++l) {
         pk = prof_begin(plan, st, EQFMM_STAGE_L2L);
         const int64_t np = int64_t(1) << (3 * (l - 1));
-        k_l2l<N, R><<<dim3(unsigned(np)), O::TPC, 0, st>>>(G, 1 << l, v.loc + W.lvl[l - 1] * O::NS,
-                                                           v.loc + W.lvl[l] * O::NS);
+        const R *p2 = l == l0 && ((hm >> (l - 1)) & 1u) ? v.loc2 + W.lvl[l - 1] * O::NS : nullptr;
+        const R *c2 = (hm >> l) & 1u ? v.loc2 + W.lvl[l] * O::NS : nullptr;
+        k_l2l<N, R><<<dim3(unsigned(np)), O::TPC, 0, st>>>(G, 1 << l, v.loc + W.lvl[l - 1] * O::NS, p2,
+                                                           v.loc + W.lvl[l] * O::NS, c2);
         EQ_CHECK(hipGetLastError());
         prof_end(plan, st, pk, EQFMM_STAGE_L2L, 0.0, 0.0);
     }

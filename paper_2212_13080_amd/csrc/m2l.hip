@@ -32,11 +32,13 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// The interaction levels of one evaluation, handled by a single launch:
-// workgroups [wg_begin[i], wg_begin[i+1]) belong to level level[i].
+// Levels of one far-field launch, finest first.  Each XCD (blockIdx % 8)
+// takes a contiguous share of every level's workgroups, the finest level's
+// first; a level marked `half` splits every list between two workgroups, the
+// second storing into the second L buffer.
 struct MxLevels {
     int nlev;
-    int level[8], ntile[8], wg_begin[9];
+    int level[8], ntile[8], nwg[8], share[8], rbeg[9], half[8];
     int64_t cell0[8];      // first cell of the level in the L array
     int64_t pcell0[8];     // first cell of the level in the haloed Phi
     float inv_side[8];
@@ -264,7 +266,7 @@ template <int N, int MODE> struct MxForm {
 template <int N, int MODE, int CH, int NSPLIT, int NST>
 __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, const int *__restrict__ mxtab,
                                                  MxLevels lv, const void *__restrict__ phipad_,
-                                                 void *__restrict__ loc_all_, int nwg)
+                                                 void *__restrict__ loc_all_, void *__restrict__ loc2_all_)
 {
     using F = MxForm<N, MODE>;
     using E = typename F::E;
@@ -287,15 +289,16 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     const E *phipad = static_cast<const E *>(phipad_);
     E *loc_all = static_cast<E *>(loc_all_);
 
-    const int per = gridDim.x >> 3;
-    int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (wg >= nwg) return;
+    const int rr = blockIdx.x >> 3;
     int li = 0;
-    while (li + 1 < lv.nlev && wg >= lv.wg_begin[li + 1]) ++li;
-    wg -= lv.wg_begin[li];
+    while (li + 1 < lv.nlev && rr >= lv.rbeg[li + 1]) ++li;
+    int wg = (blockIdx.x & 7) * lv.share[li] + (rr - lv.rbeg[li]);
+    if (wg >= lv.nwg[li]) return;
+    const int hv = lv.half[li], h = wg & hv;
+    wg >>= hv;
     const int level = lv.level[li], ntile = lv.ntile[li];
     const E inv_side = F64 ? E(lv.inv_side64[li]) : E(lv.inv_side[li]);
-    E *loc = loc_all + lv.cell0[li] * NS;
+    E *loc = (h ? static_cast<E *>(loc2_all_) : loc_all) + lv.cell0[li] * NS;
     // workgroups (tile group, parity, node block), node block fastest
     const int nb = wg % NB, tp = wg / NB;
     const int p = tp & 7, tg = tp >> 3;
@@ -305,8 +308,10 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     const int t = tg * TPW + tw;
     const bool active = t < ntile;
     const int ta = active ? t : tg * TPW;   // idle waves copy a valid tile (and store nothing)
-    constexpr int OPS = kListLen / NSPLIT;
-    const int o_begin = hs * OPS, o_end = o_begin + OPS;
+    // list part of this wave: NSPLIT parts per workgroup, twice as many (and
+    // half as long) on a level whose lists two workgroups share
+    const int ops = kListLen / (NSPLIT << hv);
+    const int o_begin = (h * NSPLIT + hs) * ops, o_end = o_begin + ops;
     if (threadIdx.x < kListLen) stab[threadIdx.x] = mxtab[(level * 8 + p) * kListLen + threadIdx.x];
     __syncthreads();
 
@@ -421,7 +426,7 @@ __global__ void __launch_bounds__(256) k_m2l_lds(const void *__restrict__ Kmx, c
     // and of 2 NCH (an even number of displacements, for the alternating
     // accumulator pairs), unrolled so that all three are constants.
     constexpr int TS = lcm_c(lcm_c(NST, 2), 2 * NCH), TD = TS / NCH;
-    static_assert(OPS % TD == 0, "pipeline trip");
+    static_assert((kListLen / NSPLIT) % TD == 0 && (kListLen / (2 * NSPLIT)) % TD == 0, "pipeline trip");
     const int s0 = o_begin * NCH;
     static_for<0, NST>([&](auto J) {
         constexpr int j = decltype(J)::value;
@@ -527,61 +532,94 @@ template <int N, int MODE> struct MxLds {
     static constexpr int NST = 3;
 };
 
+// List split of a launch over levels [l0, l1] of tiles of `cells` parents:
+// enough waves per tile to keep every SIMD busy.
+int m2l_split_of(int n3, int cells, int l0, int l1)
+{
+    const int nb = (n3 + cells - 1) / cells;
+    int64_t tiles = 0;
+    for (int l = l0; l <= l1; ++l) {
+        const int64_t Dp = (int64_t(1) << l) >> 1;
+        tiles += 8 * nb * ((Dp * Dp * Dp + cells - 1) / cells);
+    }
+    return tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4);
+}
+
+}  // namespace
+
+// Levels (bit l) whose interaction lists two workgroups share.  A launch
+// with few tiles runs in a few rounds of equal workgroups, and the coarse
+// levels' workgroups would form a last, mostly idle round; halved, they fill
+// half a round.  Every level but the finest, in launches that split lists
+// (not in the bf16 form).  The downward shifts add the two halves.
+unsigned m2l_half_levels(const eqfmm_plan *plan)
+{
+    const Geom &g = plan->g;
+    if (plan->p.precision == EQFMM_FP32_BF16FAR) return 0u;
+    const int cells = plan->p.precision == EQFMM_FP64 ? 16 : 32;
+    const int lmin = g.periodic ? 1 : 2;
+    if (m2l_split_of(g.n3, cells, lmin, g.L) < 2) return 0u;
+    unsigned m = 0;
+    for (int l = lmin; l < g.L; ++l) m |= 1u << l;
+    return m;
+}
+
+namespace {
+
 // Level table of the LDS-staged kernel: one workgroup per (group of tpw
-// tiles of `cells` parents, parity, node block).
+// tiles of `cells` parents, parity, node block[, list half]), levels finest
+// first, each level's workgroups shared out evenly over the 8 XCDs.  Returns
+// the grid size.
 int fill_levels_tg(const Geom &g, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, int cells, int nb,
-                   int tpw, MxLevels &lv)
+                   int tpw, unsigned halfmask, MxLevels &lv)
 {
     lv.nlev = lmax - lmin + 1;
-    int wgs = 0;
+    int r = 0;
     for (int i = 0; i < lv.nlev; ++i) {
-        const int l = lmin + i;
+        const int l = lmax - i;
         const int Dp = (1 << l) >> 1;
         const int64_t nparent = int64_t(Dp) * Dp * Dp;
         lv.level[i] = l;
         lv.ntile[i] = int((nparent + cells - 1) / cells);
-        lv.wg_begin[i] = wgs;
-        wgs += (lv.ntile[i] + tpw - 1) / tpw * 8 * nb;
+        lv.half[i] = int((halfmask >> l) & 1u);
+        lv.nwg[i] = ((lv.ntile[i] + tpw - 1) / tpw * 8 * nb) << lv.half[i];
+        lv.share[i] = (lv.nwg[i] + 7) / 8;
+        lv.rbeg[i] = r;
+        r += lv.share[i];
         lv.cell0[i] = lvl[l];
         lv.pcell0[i] = plvl[l];
         lv.inv_side[i] = float(double(1 << l) / g.box);
         lv.inv_side64[i] = double(1 << l) / g.box;
     }
-    lv.wg_begin[lv.nlev] = wgs;
-    return wgs;
+    lv.rbeg[lv.nlev] = r;
+    return 8 * r;
 }
 
 // The far-field products of levels [l0, l1] in one launch of form MODE.
 template <int N, int MODE>
 int launch_lds(eqfmm_plan *plan, int l0, int l1, const int64_t *lvl, const int64_t *plvl, const void *K,
-               const void *phipad, void *loc, hipStream_t st)
+               const void *phipad, void *loc, void *loc2, unsigned halfmask, hipStream_t st)
 {
     using F = MxForm<N, MODE>;
     using C = MxLds<N, MODE>;
     const Geom &g = plan->g;
-    // waves per tile: enough waves to keep every SIMD busy
-    int64_t tiles = 0;
-    for (int l = l0; l <= l1; ++l) {
-        const int64_t Dp = (int64_t(1) << l) >> 1;
-        tiles += 8 * F::NB * ((Dp * Dp * Dp + F::CELLS - 1) / F::CELLS);
-    }
-    const int split = tiles >= 4096 ? 1 : (tiles >= 1024 ? 2 : 4);
+    if (halfmask && !loc2) return EQFMM_EINVAL;
+    const int split = m2l_split_of(F::N3, F::CELLS, l0, l1);
     MxLevels lv;
-    const int nwg = fill_levels_tg(g, l0, l1, lvl, plvl, F::CELLS, F::NB, 4 / split, lv);
-    const int grid = (nwg + 7) & ~7;
+    const int grid = fill_levels_tg(g, l0, l1, lvl, plvl, F::CELLS, F::NB, 4 / split, halfmask, lv);
     const int *tab = plan->ops.mxtab;
     if (split == 1)
-        k_m2l_lds<N, MODE, C::CH, 1, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg);
+        k_m2l_lds<N, MODE, C::CH, 1, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, loc2);
     else if (split == 2)
-        k_m2l_lds<N, MODE, C::CH, 2, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg);
+        k_m2l_lds<N, MODE, C::CH, 2, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, loc2);
     else
-        k_m2l_lds<N, MODE, C::CH, 4, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, nwg);
+        k_m2l_lds<N, MODE, C::CH, 4, C::NST><<<grid, 256, 0, st>>>(K, tab, lv, phipad, loc, loc2);
     return hipGetLastError() == hipSuccess ? EQFMM_OK : EQFMM_EHIP;
 }
 
 template <int N>
 int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const float *phipad,
-              float *loc, hipStream_t st)
+              float *loc, float *loc2, hipStream_t st)
 {
     const Geom &g = plan->g;
     // bf16 inputs only on the two finest levels, which carry nearly all the
@@ -589,18 +627,22 @@ int launch_mx(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const in
     // their large, sign-cancelling vectors leaves a spurious net charge
     const bool bf = plan->p.precision == EQFMM_FP32_BF16FAR;
     const void *Kbf = static_cast<const unsigned char *>(plan->ops.Kmx) + mx_f32_bytes(g);
-    if (!bf) return launch_lds<N, MX_F32>(plan, lmin, lmax, lvl, plvl, plan->ops.Kmx, phipad, loc, st);
+    if (!bf)
+        return launch_lds<N, MX_F32>(plan, lmin, lmax, lvl, plvl, plan->ops.Kmx, phipad, loc, loc2,
+                                     m2l_half_levels(plan), st);
     const int lb = lmax - 1 > lmin ? lmax - 1 : lmin;
     int rc = EQFMM_OK;
-    if (lmin <= lb - 1) rc = launch_lds<N, MX_F32>(plan, lmin, lb - 1, lvl, plvl, plan->ops.Kmx, phipad, loc, st);
-    return rc ? rc : launch_lds<N, MX_BF16>(plan, lb, lmax, lvl, plvl, Kbf, phipad, loc, st);
+    if (lmin <= lb - 1)
+        rc = launch_lds<N, MX_F32>(plan, lmin, lb - 1, lvl, plvl, plan->ops.Kmx, phipad, loc, loc2, 0u, st);
+    return rc ? rc : launch_lds<N, MX_BF16>(plan, lb, lmax, lvl, plvl, Kbf, phipad, loc, loc2, 0u, st);
 }
 
 template <int N>
 int launch_f64(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl,
-               const double *phipad, double *loc, hipStream_t st)
+               const double *phipad, double *loc, double *loc2, hipStream_t st)
 {
-    return launch_lds<N, MX_F64>(plan, lmin, lmax, lvl, plvl, plan->ops.Kmx, phipad, loc, st);
+    return launch_lds<N, MX_F64>(plan, lmin, lmax, lvl, plvl, plan->ops.Kmx, phipad, loc, loc2,
+                                 m2l_half_levels(plan), st);
 }
 
 template <typename R, int N>
@@ -649,10 +691,11 @@ int launch_m2l_pad(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, con
 }
 
 // All interaction levels lmin..lmax in one launch (two for the bf16 mode);
-// each writes (stores) its level's local vectors.
+// each writes (stores) its level's local vectors, the levels of
+// m2l_half_levels as two halves, into loc and loc2.
 template <typename R>
 int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const int64_t *plvl, const R *phipad,
-               R *loc, hipStream_t st)
+               R *loc, R *loc2, hipStream_t st)
 {
     const Geom &g = plan->g;
     const int pk = prof_begin_m2l(plan, st);
@@ -660,9 +703,9 @@ int launch_m2l(eqfmm_plan *plan, int lmin, int lmax, const int64_t *lvl, const i
 #define EQ_CASE(NN)                                                                          \
     case NN:                                                                                 \
         if constexpr (sizeof(R) == sizeof(float))                                            \
-            rc = launch_mx<NN>(plan, lmin, lmax, lvl, plvl, phipad, loc, st);                \
+            rc = launch_mx<NN>(plan, lmin, lmax, lvl, plvl, phipad, loc, loc2, st);          \
         else                                                                                 \
-            rc = launch_f64<NN>(plan, lmin, lmax, lvl, plvl, phipad, loc, st);               \
+            rc = launch_f64<NN>(plan, lmin, lmax, lvl, plvl, phipad, loc, loc2, st);         \
         break;
     switch (g.n) {
         EQ_CASE(2) EQ_CASE(3) EQ_CASE(4) EQ_CASE(5) EQ_CASE(6) EQ_CASE(7)
@@ -683,8 +726,8 @@ template int launch_m2l_pad<float>(eqfmm_plan *, int, int, const int64_t *, cons
 template int launch_m2l_pad<double>(eqfmm_plan *, int, int, const int64_t *, const int64_t *, const double *,
                                     double *, hipStream_t);
 template int launch_m2l<float>(eqfmm_plan *, int, int, const int64_t *, const int64_t *, const float *, float *,
-                               hipStream_t);
+                               float *, hipStream_t);
 template int launch_m2l<double>(eqfmm_plan *, int, int, const int64_t *, const int64_t *, const double *,
-                                double *, hipStream_t);
+                                double *, double *, hipStream_t);
 
 }  // namespace eqfmm

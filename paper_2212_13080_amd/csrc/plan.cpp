@@ -279,6 +279,8 @@ WsLayout ws_layout(const eqfmm_plan *plan, int64_t n)
     W.plvl[g.L + 1] = pcells;
     W.phipad = take(rs * pcells * g.ns);
     W.loc = take(rs * ncells * g.ns);
+    // second halves of the coarse levels' local vectors (levels below L)
+    W.loc2 = take(rs * std::max<int64_t>(W.lvl[g.L], 1) * g.ns);
     W.sphi = take(sizeof(double) * W.fcap);
     W.snf = take(sizeof(double) * 3 * W.fcap);   // near-field sums before the far field is added
     W.sfld = take(rs * 3 * W.fcap);
