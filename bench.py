@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default=None, help="f64 | f32 | bf16far (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the side-by-side timing of the other precision forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="run one plain device copy of MB megabytes before the timed region "
                          "(reference kernel for hardware byte counters)")
@@ -68,18 +70,68 @@ def main():
     torch.cuda.set_device(dev)
     pt = torch.from_numpy(pos).to(dev)
     qt = torch.from_numpy(q).to(dev)
-    plan = eq.Plan(w.levels, w.order, w.boundary, prec, device=dev)
-    ws = plan.workspace(w.n)
     one = torch.ones((), dtype=torch.float64, device=dev)
-    # Each step's forward writes its data-dependent status to this word
-    # instead of blocking on it; it is checked after every synchronisation
-    # (every step computes on the same inputs).
-    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    peak_key = {eq.FP64: "fp64_mfma", eq.FP32: "fp32_mfma", eq.FP32_BF16FAR: "bf16_mfma"}
+    dtype_name = {eq.FP64: "f64", eq.FP32: "f32", eq.FP32_BF16FAR: "f32+bf16"}
 
-    def step():
-        E, phi, field = plan.forward(pt, qt, ws=ws, status=status)
-        dx, dq = plan.backward(qt, one, ws=ws)
-        return E, phi, field, dx, dq
+    def run_form(prec, steps, warmup, stage_breakdown):
+        """Time `steps` steps of one precision form; returns the timing, the
+        far-field launch statistics and the last step's outputs."""
+        plan = eq.Plan(w.levels, w.order, w.boundary, prec, device=dev)
+        ws = plan.workspace(w.n)
+        # Each step's forward writes its data-dependent status to this word
+        # instead of blocking on it; it is checked after every
+        # synchronisation (every step computes on the same inputs).
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+        def step():
+            E, phi, field = plan.forward(pt, qt, ws=ws, status=status)
+            dx, dq = plan.backward(qt, one, ws=ws)
+            return E, phi, field, dx, dq
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        plan.check_status(status)
+        # only the far-field launch is bracketed by events in the timed
+        # region (an event pair costs a few microseconds)
+        plan.profile(["m2l"])
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.check_status(status)
+        prof = plan.profile_read()
+        plan.profile(False)
+        ms = (t1 - t0) * 1e3 / steps
+        print(f"[bench] {w.name} {dtype_name[prec]}: {ms:.3f} ms/step, {w.n / (ms * 1e-3):.4g} particles/s",
+              file=sys.stderr, flush=True)
+        if stage_breakdown:
+            # per-stage breakdown, in steps of their own after the timed region
+            plan.profile(True)
+            nb = min(steps, 5)
+            for _ in range(nb):
+                step()
+            stages = plan.profile_read()
+            plan.profile(False)
+            plan.check_status(status)
+            for k, v in stages.items():
+                if v["launches"]:
+                    print(f"[bench]   {k:8s} {v['ms'] / nb:8.4f} ms/step  launches/step "
+                          f"{v['launches'] / nb:.0f}", file=sys.stderr, flush=True)
+        # dominant kernel: the far-field products of all levels (one launch
+        # per step; two in the bf16 mode)
+        m2l = prof["m2l"]
+        achieved = m2l["flops"] / (m2l["ms"] * 1e-3) / 1e12 if m2l["ms"] > 0 else 0.0
+        roof = {"kernel": "m2l", "bound": "mfma", "achieved": round(achieved, 3),
+                "peak": PEAKS[peak_key[prec]], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAKS[peak_key[prec]], 4),
+                "avg_launch_ms": round(m2l["ms"] / max(m2l["launches"], 1), 5),
+                "launches_per_step": m2l["launches"] / steps,
+                "algorithmic_flops_per_step": m2l["flops"] / steps}
+        del plan, ws
+        return ms, roof, out
 
     if args.calibrate_copy:
         src = torch.empty(args.calibrate_copy * 2 ** 20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -88,48 +140,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    plan.check_status(status)
-    # only the far-field launch is bracketed by events in the timed region
-    # (an event pair costs a few microseconds)
-    plan.profile(["m2l"])
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.check_status(status)
-    prof = plan.profile_read()
-    plan.profile(False)
-    ms = (t1 - t0) * 1e3 / args.steps
-    value = w.n / (ms * 1e-3)
-    print(f"[bench] {w.name}: {ms:.3f} ms/step, {value:.4g} particles/s", file=sys.stderr, flush=True)
-    # per-stage breakdown, in steps of their own after the timed region
-    plan.profile(True)
-    nb = min(args.steps, 5)
-    for _ in range(nb):
-        step()
-    stages = plan.profile_read()
-    plan.profile(False)
-    plan.check_status(status)
-    for k, v in stages.items():
-        if v["launches"]:
-            print(f"[bench]   {k:8s} {v['ms'] / nb:8.4f} ms/step  launches/step "
-                  f"{v['launches'] / nb:.0f}", file=sys.stderr, flush=True)
 
-    # dominant kernel: the far-field products of all levels (one launch per
-    # step; two in the bf16 mode)
-    m2l = prof["m2l"]
-    peak_key = {eq.FP64: "fp64_mfma", eq.FP32: "fp32_mfma", eq.FP32_BF16FAR: "bf16_mfma"}[prec]
-    achieved = m2l["flops"] / (m2l["ms"] * 1e-3) / 1e12 if m2l["ms"] > 0 else 0.0
-    roofline = {"kernel": "m2l", "bound": "mfma", "achieved": round(achieved, 3),
-                "peak": PEAKS[peak_key], "unit": "TFLOP/s", "frac": round(achieved / PEAKS[peak_key], 4),
-                "traffic": counter_traffic(w.name, prec),
-                "avg_launch_ms": round(m2l["ms"] / max(m2l["launches"], 1), 5),
-                "launches_per_step": m2l["launches"] / args.steps,
-                "algorithmic_flops_per_step": m2l["flops"] / args.steps}
+    ms, roofline, out = run_form(prec, args.steps, args.warmup, True)
+    value = w.n / (ms * 1e-3)
+    roofline = dict(roofline, traffic=counter_traffic(w.name, prec))
+    # the three forms side by side (plain FP64, FP32 + adjoint, BF16 far
+    # field + adjoint), each on the same inputs
+    forms = {}
+    if not args.no_forms:
+        for p in (eq.FP64, eq.FP32, eq.FP32_BF16FAR):
+            if p == prec:
+                fms, froof, fout = ms, roofline, out
+            else:
+                fms, froof, fout = run_form(p, max(args.steps // 4, 1), max(args.warmup // 4, 1), False)
+            forms[dtype_name[p]] = {"value": round(w.n / (fms * 1e-3), 1), "ms_per_step": round(fms, 4),
+                                    "m2l_frac": froof["frac"], "m2l_peak": froof["peak"],
+                                    "m2l_avg_launch_ms": froof["avg_launch_ms"], "_out": fout}
 
     E, phi, field, dx, dq = out
     result = {
@@ -137,7 +163,7 @@ def main():
         "value": round(value, 1), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {eq.FP64: "f64", eq.FP32: "f32", eq.FP32_BF16FAR: "f32+bf16"}[prec],
+        "dtype": dtype_name[prec],
         "data": "synthetic",
         "config": {"workload": w.name, "n_charges": w.n, "levels": w.levels, "order": w.order,
                    "boundary": workloads.BOUNDARY_NAMES[w.boundary]},
@@ -153,10 +179,20 @@ def main():
                                   "kind": "oracle",
                                   "sample": f"one full evaluation of the same workload ({w.n} charges, "
                                             f"potential+field+energy), {tc:.2f} s"}
-        F = (-dx.double().cpu().numpy())
         Fr = q[:, None] * ref["field"]
-        result["rel_rms_force_err"] = float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr))
-        result["rel_energy_err"] = float(abs(E.item() - ref["energy"]) / abs(ref["energy"]))
+
+        def errors(o):
+            F = -o[3].double().cpu().numpy()
+            return (float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr)),
+                    float(abs(o[0].item() - ref["energy"]) / abs(ref["energy"])))
+
+        result["rel_rms_force_err"], result["rel_energy_err"] = errors(out)
+        for f in forms.values():
+            f["rel_rms_force_err"], f["rel_energy_err"] = errors(f["_out"])
+    for f in forms.values():
+        f.pop("_out")
+    if forms:
+        result["forms"] = forms
     print(json.dumps(result), flush=True)
 
 

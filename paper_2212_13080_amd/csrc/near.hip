@@ -33,13 +33,32 @@ template <int N> struct NearShape {
     static constexpr int NS = (N3 + 15) & ~15;
 };
 
+// Compensated running sum (Knuth's two-sum): the rounding error of every
+// addition is carried in c, so folding m block partials into it loses
+// O(eps) in total instead of O(m eps).  Each per-target sum is two-level:
+// plain sums over short blocks of sources (one neighbour segment, at most
+// kBlock sources) or over one plane of basis nodes, folded in here.
+template <typename C> struct CSum {
+    C s = C(0), c = C(0);
+    __device__ __forceinline__ void add(C x)
+    {
+        const C t = s + x;
+        const C bp = t - s;
+        c += (s - (t - bp)) + (x - bp);
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return double(s) + double(c); }
+};
+
+constexpr int kBlock = 32;     // sources per plain block in the unstaged loops
 constexpr int kChunk = 1024;   // staged sources of one row block
 constexpr int kDense = 256;    // row blocks with this many targets go to k_near_dense
 constexpr int kMaxRB = 64;     // cells per row block at most
 
 template <int N, typename C, typename R>
 __device__ __forceinline__ void l2p_part(const R *t_, const R *den_, const R *Lc, double ud, double vd,
-                                         double wd, C inv_s, int sl, int S, C &ph, C &f0, C &f1, C &f2)
+                                         double wd, double inv_s, int sl, int S, double &ph, double &f0,
+                                         double &f1, double &f2)
 {
     C t[N], den[N], gx[N], gy[N], gz[N], dx[N], dy[N], dz[N];
 #pragma unroll
@@ -68,8 +87,9 @@ __device__ __forceinline__ void l2p_part(const R *t_, const R *den_, const R *Lc
         gz[i] = den[i] * r;
         dz[i] = den[i] * dr;
     }
-    C a0 = C(0), a1 = C(0), a2 = C(0), a3 = C(0);
-    for (int k = sl; k < N; k += S)
+    CSum<C> a0, a1, a2, a3;
+    for (int k = sl; k < N; k += S) {
+        C b0 = C(0), b1 = C(0), b2 = C(0);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             C s0 = C(0), s1 = C(0);
@@ -79,15 +99,19 @@ __device__ __forceinline__ void l2p_part(const R *t_, const R *den_, const R *Lc
                 s0 += gx[i] * l;
                 s1 += dx[i] * l;
             }
-            a0 += gz[k] * gy[j] * s0;
-            a1 += gz[k] * gy[j] * s1;
-            a2 += gz[k] * dy[j] * s0;
-            a3 += dz[k] * gy[j] * s0;
+            b0 += gy[j] * s0;
+            b1 += gy[j] * s1;
+            b2 += dy[j] * s0;
         }
-    ph += a0;
-    f0 -= a1 * inv_s;
-    f1 -= a2 * inv_s;
-    f2 -= a3 * inv_s;
+        a0.add(gz[k] * b0);
+        a1.add(gz[k] * b1);
+        a2.add(gz[k] * b2);
+        a3.add(dz[k] * b0);
+    }
+    ph += a0.value();
+    f0 -= a1.value() * inv_s;
+    f1 -= a2.value() * inv_s;
+    f2 -= a3.value() * inv_s;
 }
 
 template <typename R> __device__ __forceinline__ R rsqrt_t(R x);
@@ -143,6 +167,35 @@ __device__ __forceinline__ void p2p_range(const double *lx, const double *lv, co
         const C ez = C((wz - lw[j]) * sd);
         const bool self = SELF_BY_INDEX ? j == oself : lpar[j] == par;
         p2p_term<C>(ex, ey, ez, C(lq[j]), self, ph, f0, f1, f2);
+    }
+}
+
+// Sources [j0, j1) of one segment read from global memory (dense
+// neighbourhoods), in plain blocks of kBlock folded into the compensated
+// sums; targets evaluated in double (dbl) sum in double throughout.
+template <typename R>
+__device__ __forceinline__ void p2p_global(const double *su, const double *sv, const double *sw, const R *sq,
+                                           const int *spar, const int *sleaf, int D, int j0, int j1, int shift,
+                                           double ud, int tx, double vy, double wz, int par, bool dbl, double sd,
+                                           CSum<R> &aph, CSum<R> &af0, CSum<R> &af1, CSum<R> &af2, double &dph,
+                                           double &df0, double &df1, double &df2)
+{
+    for (int jb = j0; jb < j1; jb += kBlock) {
+        const int je = jb + kBlock < j1 ? jb + kBlock : j1;
+        R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
+        for (int j = jb; j < je; ++j) {
+            const double ex = ud + double(tx - ((sleaf[j] & (D - 1)) + shift)) - su[j];
+            const double ey = vy - sv[j], ez = wz - sw[j];
+            const bool self = spar[j] == par;
+            if (dbl) p2p_term<double>(ex * sd, ey * sd, ez * sd, double(sq[j]), self, dph, df0, df1, df2);
+            else p2p_term<R>(R(ex * sd), R(ey * sd), R(ez * sd), sq[j], self, ph, f0, f1, f2);
+        }
+        if (!dbl) {
+            aph.add(ph);
+            af0.add(f0);
+            af1.add(f1);
+            af2.add(f2);
+        }
     }
 }
 
@@ -330,7 +383,7 @@ __global__ void __launch_bounds__(256) k_near(Geom g, int RB, const int *leafsta
         const int tx = leaf & (D - 1);
         const double xt = ud + double(tx);
         const bool dbl = mixed && smask[par];
-        R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
+        CSum<R> aph, af0, af1, af2;
         double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
         if (act) {
             for (int k = 0; k < nseg; ++k) {
@@ -351,6 +404,7 @@ __global__ void __launch_bounds__(256) k_near(Geom g, int RB, const int *leafsta
                 }
                 const double vy = vd - sg.dy, wz = wd - sg.dz;
                 if (staged) {
+                    R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
                     const int off = sbase[k] - sj0[k];
                     // one fragment per charge: the self pair is the target's own slot
                     const int oself = t + off;
@@ -363,20 +417,19 @@ __global__ void __launch_bounds__(256) k_near(Geom g, int RB, const int *leafsta
                     else
                         p2p_range<R, R, UNWRAP, true>(lx, lv, lw, lq, lpar, ldx, j0 + off + sl, j1 + off, S, xt,
                                                       ud, tx, vy, wz, par, oself, sd, ph, f0, f1, f2);
+                    aph.add(ph);
+                    af0.add(f0);
+                    af1.add(f1);
+                    af2.add(f2);
                 } else {
-                    for (int j = j0; j < j1; ++j) {
-                        const double ex = ud + double(tx - ((sleaf[j] & (D - 1)) + sg.shift)) - su[j];
-                        const double ey = vy - sv[j], ez = wz - sw[j];
-                        const bool self = spar[j] == par;
-                        if (dbl) p2p_term<double>(ex * sd, ey * sd, ez * sd, double(sq[j]), self, dph, df0, df1, df2);
-                        else p2p_term<R>(R(ex * sd), R(ey * sd), R(ez * sd), sq[j], self, ph, f0, f1, f2);
-                    }
+                    p2p_global<R>(su, sv, sw, sq, spar, sleaf, D, j0, j1, sg.shift, ud, tx, vy, wz, par, dbl, sd,
+                                  aph, af0, af1, af2, dph, df0, df1, df2);
                 }
             }
         }
         // add the slices of each target in a fixed order
-        double o0 = dbl ? dph : double(ph), o1 = dbl ? df0 : double(f0);
-        double o2 = dbl ? df1 : double(f1), o3 = dbl ? df2 : double(f2);
+        double o0 = dbl ? dph : aph.value(), o1 = dbl ? df0 : af0.value();
+        double o2 = dbl ? df1 : af1.value(), o3 = dbl ? df2 : af2.value();
         if (S > 1) {
             __syncthreads();
             if (sl > 0) {
@@ -426,7 +479,7 @@ __global__ void __launch_bounds__(256) k_near_dense(Geom g, int RB, const int *n
     const double ud = su[t], vd = sv[t], wd = sw[t];
     const int par = spar[t];
     const bool dbl = sizeof(R) == sizeof(float) && g.continuous && smask[par];
-    R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
+    CSum<R> aph, af0, af1, af2;
     double dph = 0.0, df0 = 0.0, df1 = 0.0, df2 = 0.0;
     Seg segs[27];
     const int nseg = row_segments(g, y, z, tx, tx + 1, segs);
@@ -435,18 +488,13 @@ __global__ void __launch_bounds__(256) k_near_dense(Geom g, int RB, const int *n
         int j0, j1;
         window(leafstart, sg, tx, j0, j1);
         const double vy = vd - sg.dy, wz = wd - sg.dz;
-        for (int j = j0; j < j1; ++j) {
-            const double ex = ud + double(tx - ((sleaf[j] & (D - 1)) + sg.shift)) - su[j];
-            const double ey = vy - sv[j], ez = wz - sw[j];
-            const bool self = spar[j] == par;
-            if (dbl) p2p_term<double>(ex * sd, ey * sd, ez * sd, double(sq[j]), self, dph, df0, df1, df2);
-            else p2p_term<R>(R(ex * sd), R(ey * sd), R(ez * sd), sq[j], self, ph, f0, f1, f2);
-        }
+        p2p_global<R>(su, sv, sw, sq, spar, sleaf, D, j0, j1, sg.shift, ud, tx, vy, wz, par, dbl, sd, aph, af0,
+                      af1, af2, dph, df0, df1, df2);
     }
-    sphi[t] = dbl ? dph : double(ph);
-    snf[3 * t + 0] = dbl ? df0 : double(f0);
-    snf[3 * t + 1] = dbl ? df1 : double(f1);
-    snf[3 * t + 2] = dbl ? df2 : double(f2);
+    sphi[t] = dbl ? dph : aph.value();
+    snf[3 * t + 0] = dbl ? df0 : af0.value();
+    snf[3 * t + 1] = dbl ? df1 : af1.value();
+    snf[3 * t + 2] = dbl ? df2 : af2.value();
 }
 
 // Far field at the fragments (a7), added to their near-field sums: Psi of
@@ -465,16 +513,9 @@ __global__ void __launch_bounds__(256) k_l2p(Geom g, const R *t_, const R *den_,
     const double ud = su[t], vd = sv[t], wd = sw[t];
     const bool dbl = sizeof(R) == sizeof(float) && g.continuous && smask[spar[t]];
     const R *Lc = locL + int64_t(sleaf[t]) * O::NS;
-    double a0, a1, a2, a3;
-    if (dbl) {
-        double ph = 0.0, f0 = 0.0, f1 = 0.0, f2 = 0.0;
-        l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, 0, 1, ph, f0, f1, f2);
-        a0 = ph, a1 = f0, a2 = f1, a3 = f2;
-    } else {
-        R ph = R(0), f0 = R(0), f1 = R(0), f2 = R(0);
-        l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, R(1.0 / sd), 0, 1, ph, f0, f1, f2);
-        a0 = ph, a1 = f0, a2 = f1, a3 = f2;
-    }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (dbl) l2p_part<N, double>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, 0, 1, a0, a1, a2, a3);
+    else l2p_part<N, R>(t_, den_, Lc, ud, vd, wd, 1.0 / sd, 0, 1, a0, a1, a2, a3);
     sphi[t] += a0;
     sfld[3 * t + 0] = R(snf[3 * t + 0] + a1);
     sfld[3 * t + 1] = R(snf[3 * t + 1] + a2);
