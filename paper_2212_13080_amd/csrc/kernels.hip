@@ -301,24 +301,14 @@ __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const d
     const double qi = q[i];
     int f = fstart[i];
     if (!split) {   // one piece of weight 1 in cell c (as axis_pieces gives it)
+        // only the owner goes to the sorted slot here; k_fill writes the
+        // rest of the slot in slot order (coalesced stores)
         const int leaf = c[0] + g.D * (c[1] + g.D * c[2]);
         const int slot = leafstart[leaf] + atomicAdd(&cursor[leaf], 1);
-        const double s = g.s_leaf;
-        if (slot < fcap) {
-            su[slot] = v[0] / s - c[0];
-            sv[slot] = v[1] / s - c[1];
-            sw[slot] = v[2] / s - c[2];
-            sq[slot] = R(qi);
-            spar[slot] = int(i);
-            sleaf[slot] = leaf;
-        }
-        if (f < fcap) {
-            gslot[f] = slot < fcap ? slot : 0;
-            gw[f] = 1.0;
-            gdw[3 * int64_t(f) + 0] = 0.0;
-            gdw[3 * int64_t(f) + 1] = 0.0;
-            gdw[3 * int64_t(f) + 2] = 0.0;
-        }
+        if (slot < fcap) spar[slot] = int(i);
+        // an unsplit charge's weight is 1 and its weight gradient 0: the
+        // gather and the adjoint take them from its empty split mask
+        if (f < fcap) gslot[f] = slot < fcap ? slot : 0;
         return;
     }
     Pieces<N> P[3];
@@ -346,6 +336,34 @@ __global__ void __launch_bounds__(256) k_emit(Geom g, const double *seg, const d
                     gdw[3 * int64_t(f) + 2] = ox * oy * P[2].dom[kz];
                 }
             }
+}
+
+// The sorted slots of unsplit charges, in slot order: the owner written by
+// k_emit gives the charge, whose cell-local coordinates, charge and cell are
+// computed again exactly as k_emit computes them.  Split charges' slots were
+// written whole by k_emit.  nfrag: the (clamped) slot count on the device.
+template <typename R>
+__global__ void __launch_bounds__(256) k_fill(Geom g, const int *nfrag, const double *pos, const double *q,
+                                              const unsigned char *smask, const int *spar, double *su, double *sv,
+                                              double *sw, R *sq, int *sleaf)
+{
+    const int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (slot >= *nfrag) return;
+    const int i = spar[slot];
+    if (smask[i]) return;
+    double v[3];
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        box_coord(g, pos[3 * int64_t(i) + a], a, v[a]);
+        axis_split(g, v[a], c[a]);
+    }
+    const double s = g.s_leaf;
+    su[slot] = v[0] / s - c[0];
+    sv[slot] = v[1] / s - c[1];
+    sw[slot] = v[2] / s - c[2];
+    sq[slot] = R(q[i]);
+    sleaf[slot] = c[0] + g.D * (c[1] + g.D * c[2]);
 }
 
 // ------------------------------------------------------------- prefix sums
@@ -625,7 +643,7 @@ __global__ void __launch_bounds__(256) k_gather(int64_t n, const double *q, cons
         double ph = 0.0, fe[3] = {0.0, 0.0, 0.0};
         for (int f = f0; f < f1; ++f) {
             const int sl = gslot[f];
-            const double w = gw[f], pv = sphi[sl];
+            const double w = mask ? gw[f] : 1.0, pv = sphi[sl];
             ph += w * pv;
             for (int a = 0; a < 3; ++a) {
                 if (mask & (1 << a)) fe[a] -= gdw[3 * int64_t(f) + a] * pv;
@@ -692,7 +710,7 @@ __global__ void __launch_bounds__(256) k_adjoint(int64_t n, const double *q, con
     double ph = 0.0, gx[3] = {0.0, 0.0, 0.0};
     for (int f = f0; f < f1; ++f) {
         const int sl = gslot[f];
-        const double w = gw[f], pv = sphi[sl];
+        const double w = mask ? gw[f] : 1.0, pv = sphi[sl];
         ph += w * pv;
         for (int a = 0; a < 3; ++a) {
             if (mask & (1 << a)) gx[a] += gdw[3 * int64_t(f) + a] * pv;
@@ -805,6 +823,9 @@ int forward_impl(eqfmm_plan *plan, int64_t n, const double *pos, const double *q
     k_emit<N, R><<<blocks(n, 256), 256, 0, st>>>(g, ops.seg64, ops.seg_den64, n, pos, q, v.fstart,
                                                  v.leafstart, v.cursor, v.su, v.sv, v.sw, v.sq,
                                                  v.spar, v.sleaf, v.gslot, v.gw, v.gdw, W.fcap);
+    EQ_CHECK(hipGetLastError());
+    k_fill<R><<<blocks(W.fcap, 256), 256, 0, st>>>(g, v.leafstart + nleaf, pos, q, v.smask, v.spar, v.su, v.sv,
+                                                   v.sw, v.sq, v.sleaf);
     EQ_CHECK(hipGetLastError());
     prof_end(plan, st, pk, EQFMM_STAGE_BIN, 0.0, double(n) * 104.0);
 
