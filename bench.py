@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default=None, help="f64 | f32 | bf16far (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--node-shrink", type=float, default=1.0,
+                    help="spacing of the n-division points relative to the cell (Sec. 4.1: 1/1.2)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the side-by-side timing of the other precision forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
@@ -77,7 +79,7 @@ def main():
     def run_form(prec, steps, warmup, stage_breakdown):
         """Time `steps` steps of one precision form; returns the timing, the
         far-field launch statistics and the last step's outputs."""
-        plan = eq.Plan(w.levels, w.order, w.boundary, prec, device=dev)
+        plan = eq.Plan(w.levels, w.order, w.boundary, prec, node_shrink=args.node_shrink, device=dev)
         ws = plan.workspace(w.n)
         # Each step's forward writes its data-dependent status to this word
         # instead of blocking on it; it is checked after every
@@ -166,14 +168,14 @@ def main():
         "dtype": dtype_name[prec],
         "data": "synthetic",
         "config": {"workload": w.name, "n_charges": w.n, "levels": w.levels, "order": w.order,
-                   "boundary": workloads.BOUNDARY_NAMES[w.boundary]},
+                   "boundary": workloads.BOUNDARY_NAMES[w.boundary], "node_shrink": args.node_shrink},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         t0 = time.perf_counter()
-        ref = oracle.fmm(pos, q, w.levels, w.order, w.boundary)
+        ref = oracle.fmm(pos, q, w.levels, w.order, w.boundary, node_shrink=args.node_shrink)
         tc = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(w.n / tc, 1), "unit": "particles/s", "cores": threads,
                                   "kind": "oracle",

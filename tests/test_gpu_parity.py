@@ -286,3 +286,23 @@ def test_bf16_far_field_error_bound(case):
     # split derivative amplifies the far-field input rounding by ~s/(2d)
     bound = 2e-2 if boundary in (FREE_C, PER_C) else 5e-3
     assert e_phi < bound and e_fld < bound and e_E < 1e-4
+
+
+# Sec. 4.1: the n-division points inside the cube, spacing scaled by 1/1.2.
+# FP64 is held to 1e-10.  In FP32 the bar is 1e-5 at n = 4; at n = 5 and 6
+# the bound is 1e-4: with the points inside the cube the child-to-parent
+# shift extrapolates, and its absolute column sums per axis grow from 2.17
+# to 3.71 (n = 5) and from 2.99 to 7.18 (n = 6), so the float rounding of
+# the upward and downward passes is amplified about (3.71/2.17)^3 = 5 and
+# (7.18/2.99)^3 = 14 times more per level than with the default points.
+@pytest.mark.parametrize("precision", [eq.FP64, eq.FP32], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", [("c2", 20000, 3, 4, FREE, 0.0, 1e-5), ("c3", 8192, 3, 5, PER_C, 0.0, 1e-4),
+                                  ("c4", 8192, 3, 6, FREE_C, 0.0, 1e-4)],
+                         ids=lambda c: f"{c[0]}-N{c[1]}-l{c[2]}-n{c[3]}-b{c[4]}")
+def test_parity_reduced_nodes(case, precision):
+    key, n, levels, order, boundary, d, tol32 = case
+    print(f"case {case} precision {precision} node_shrink 1/1.2", flush=True)
+    _, pos, q = case_inputs(key, n, levels)
+    r = oracle.fmm(pos, q, levels, order, boundary, split_d=d, node_shrink=1 / 1.2)
+    g = run_gpu(pos, q, levels, order, boundary, precision, split_d=d, node_shrink=1 / 1.2)
+    check(g, r, q, TOL[eq.FP64] if precision == eq.FP64 else tol32, f"{key} {precision} shrink")

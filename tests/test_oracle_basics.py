@@ -151,3 +151,24 @@ def test_bilinear_is_symmetric_and_exact_on_nodes(orc):
     a = orc.replace(n, lo1, 1.0, p1, [1.0])
     b = orc.replace(n, lo2, 1.0, p2, [-2.0])
     assert np.isclose(orc.bilinear(n, lo1, 1.0, lo2, 1.0, a, b), -2.0 / np.linalg.norm(p1 - p2), rtol=1e-14)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_invariance_3d_reduced_nodes(orc, n):
+    # Eq. (11) with the reduced arrangement of Sec. 4.1 (spacing x 1/1.2,
+    # points inside the cube): replacing in a child and shifting to the
+    # parent still equals replacing directly in the parent
+    sig = 1 / 1.2
+    rng = np.random.default_rng(40 + n)
+    t = orc.nodes(n, sig)
+    assert np.isclose(t.max() - t.min(), sig) and np.isclose(t.mean(), 0.5)
+    plo, ps = np.array([0.5, 0.0, 0.25]), 0.25
+    for b in itertools.product((0, 1), repeat=3):
+        clo = plo + ps / 2 * np.array(b)
+        pos = clo + ps / 2 * rng.random((9, 3))
+        q = rng.uniform(-1, 1, 9)
+        child = orc.replace(n, clo, ps / 2, pos, q, sigma=sig)
+        G = [orc.shift_1d(clo[a] + ps / 2 * t, plo[a] + ps * t) for a in range(3)]
+        shifted = orc.shift_3d(n, G[0], G[1], G[2], child)
+        direct = orc.replace(n, plo, ps, pos, q, sigma=sig)
+        assert np.abs(shifted - direct).max() <= 1e-12 * np.abs(direct).max()
