@@ -132,22 +132,40 @@ class _Energy(torch.autograd.Function):
         ws = torch.empty(max(plan.workspace_bytes(q.numel()), 256), dtype=torch.uint8, device=plan.device)
         E, phi, field = plan.forward(pos, q, ws=ws)
         ctx.plan, ctx.ws = plan, ws
-        ctx.save_for_backward(q)
-        ctx.mark_non_differentiable(phi, field)
+        ctx.save_for_backward(pos, q)
+        # In free space phi is linear in q with a symmetric matrix (the
+        # method's pair terms are symmetric, Sec. 2.2), so its vector-Jacobian
+        # product in q is phi of the upstream gradient taken as charges.  The
+        # periodic modes' shape terms are not symmetric: phi stays constant
+        # there, as does the field everywhere.
+        if plan.boundary in (FREE, FREE_CONTINUOUS):
+            ctx.mark_non_differentiable(field)
+        else:
+            ctx.mark_non_differentiable(phi, field)
+        ctx.set_materialize_grads(False)
         ctx.pos_dtype, ctx.q_dtype = pos.dtype, q.dtype
         return E, phi, field
 
     @staticmethod
     def backward(ctx, gE, gphi, gfield):
-        (q,) = ctx.saved_tensors
-        if gE is None:
-            return None, None, None
-        dx, dq = ctx.plan.backward(q, gE, ws=ctx.ws, want_dx=ctx.needs_input_grad[0],
-                                   want_dq=ctx.needs_input_grad[1])
+        pos, q = ctx.saved_tensors
+        dx = dq = None
+        if gE is not None:
+            dx, dq = ctx.plan.backward(q, gE, ws=ctx.ws, want_dx=ctx.needs_input_grad[0],
+                                       want_dq=ctx.needs_input_grad[1])
+        if gphi is not None:
+            if ctx.needs_input_grad[0]:
+                raise NotImplementedError("the gradient of phi with respect to the positions is not provided; "
+                                          "only E is differentiable in the positions")
+            if ctx.needs_input_grad[1]:
+                # the plan's own workspace: ctx.ws keeps the forward's state
+                _, vq, _ = ctx.plan.forward(pos, gphi, want_field=False)
+                dq = vq if dq is None else dq + vq
         return (dx.to(ctx.pos_dtype) if dx is not None else None,
                 dq.to(ctx.q_dtype) if dq is not None else None, None)
 
 
 def energy(pos, q, plan):
-    """(E, phi, field) with E differentiable in pos and q (phi, field are not)."""
+    """(E, phi, field): E differentiable in pos and q; in the free modes phi
+    differentiable in q (not in pos); field constant."""
     return _Energy.apply(pos, q, plan)

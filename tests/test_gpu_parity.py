@@ -306,3 +306,44 @@ def test_parity_reduced_nodes(case, precision):
     r = oracle.fmm(pos, q, levels, order, boundary, split_d=d, node_shrink=1 / 1.2)
     g = run_gpu(pos, q, levels, order, boundary, precision, split_d=d, node_shrink=1 / 1.2)
     check(g, r, q, TOL[eq.FP64] if precision == eq.FP64 else tol32, f"{key} {precision} shrink")
+
+
+# phi is linear in q with a symmetric matrix in the free modes, so the
+# gradient of sum_i c_i phi_i in q is phi evaluated with charges c.  Checked
+# against the oracle (phi of c plus phi of q for the loss c.phi + E) and,
+# in FP64, against central differences in q, which are exact up to rounding
+# for a loss that is quadratic in q.
+@pytest.mark.parametrize("precision", [eq.FP64, eq.FP32], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", [("c2", 8192, 3, 4, FREE, 0.0), ("c4", 8192, 3, 6, FREE_C, 0.0)],
+                         ids=lambda c: f"{c[0]}-N{c[1]}-l{c[2]}-n{c[3]}-b{c[4]}")
+def test_phi_vjp_in_q(case, precision):
+    key, n, levels, order, boundary, d = case
+    print(f"case {case} precision {precision} phi vjp", flush=True)
+    _, pos, q = case_inputs(key, n, levels)
+    c = np.random.default_rng(11).uniform(-1, 1, n)
+    ref = oracle.fmm(pos, c, levels, order, boundary)["phi"] + oracle.fmm(pos, q, levels, order, boundary)["phi"]
+    plan = eq.Plan(levels, order, boundary, precision)
+    pt = torch.from_numpy(pos).cuda()
+    qt = torch.from_numpy(q).cuda().requires_grad_(True)
+    ct = torch.from_numpy(c).cuda()
+    E, phi, _ = eq.energy(pt, qt, plan)
+    ((ct * phi.double()).sum() + E).backward()
+    gq = qt.grad.cpu().numpy()
+    if precision == eq.FP64:
+        assert rel_max(gq, ref) <= 1e-10
+        v = np.random.default_rng(12).uniform(-1, 1, n)
+        h = 1e-3
+
+        def loss(qq):
+            Ev, phv, _ = plan.forward(pt, torch.from_numpy(qq).cuda())
+            return float((ct * phv).sum().item() + Ev.item())
+
+        fd = (loss(q + h * v) - loss(q - h * v)) / (2 * h)
+        assert abs(fd - np.dot(gq, v)) <= 1e-9 * np.abs(gq * v).sum()
+    else:
+        assert rel_rms(gq, ref) <= 1e-5
+    # phi is not differentiable in the positions: asking for it fails loudly
+    pt2 = pt.clone().requires_grad_(True)
+    E2, phi2, _ = eq.energy(pt2, qt, plan)
+    with pytest.raises(NotImplementedError):
+        (ct * phi2.double()).sum().backward()
