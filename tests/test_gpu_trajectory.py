@@ -8,7 +8,7 @@ error), every output is finite, and the adjoint identities E = 1/2 sum q phi
 and dE/dq = phi hold.  At the first and the last step the FP32 forces are
 compared with the FP64 form on the same positions (1e-5 relative RMS).  The
 time per evaluation (forward + adjoint, positions already on the device) is
-written to gpurun_out/c5_trajectory.txt.
+recorded in the test output folder.
 """
 import os
 import time
