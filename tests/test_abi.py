@@ -60,3 +60,14 @@ def test_host_only_calls(lib):
     bad.levels, bad.order, bad.split_d = 3, 4, 0.1      # 2d >= leaf side
     with pytest.raises(native.EqfmmError):
         native.eqfmm_plan_create(bad)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # bench.py measures one GPU; a request for more exits with a message
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
